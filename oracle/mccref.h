@@ -1,0 +1,93 @@
+/*
+ * mccref: plain sequential CPU oracle for median consensus clustering.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code defines the expected result of the
+ * GPU library; it is called by the tests, by the package's smoke check and
+ * by the benchmark's CPU-baseline leg, never by the product path.  It shares
+ * no code, header, table or helper with the GPU library.
+ *
+ * Paper: "Parallel Algorithms for Median Consensus Clustering in Complex
+ * Networks" (Hussain, Halappanavar, Chatterjee, Radicchi, Fortunato, Azad).
+ *
+ * All pointers are HOST pointers.  Labels are one contiguous partition-major
+ * array: labels[i * n + v] is the cluster of vertex v in input partition i.
+ * Any label value >= 0 is allowed.  Graphs are CSR: row_ptr[n + 1] (int64),
+ * col[nnz] (int32); arcs are read as given (self-loops ignored, duplicate
+ * arcs harmless).
+ *
+ * Return codes: 0 success, MCCREF_EINVAL bad argument, MCCREF_EGRAPH bad
+ * CSR, MCCREF_ENOMEM allocation failure.
+ */
+#ifndef MCCREF_H
+#define MCCREF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCCREF_EINVAL (-1)
+#define MCCREF_EGRAPH (-2)
+#define MCCREF_ENOMEM (-3)
+
+typedef struct {
+  /* in */
+  int32_t max_rounds;        /* cap on scoring passes; 0 means 1000 */
+  int32_t literal_self_term; /* 1: score with the paper's printed sum over all
+                                u including u = v (adds k to every gain);
+                                0: exact gain (default) */
+  /* out */
+  int32_t passes;            /* scoring passes run, including the last one
+                                that finds no improving move */
+  int32_t converged;         /* 1 if stopped because no vertex can move */
+  int32_t fallback_rounds;   /* passes whose full batch did not lower O */
+  int32_t clusters;          /* distinct clusters in the output */
+  int64_t moves;             /* committed vertex moves, all passes */
+  int64_t candidate_evals;   /* sum over passes and vertices of |cand(v)| */
+  int64_t objective_init;    /* O(init) = sum_i Mirkin(init, P_i) */
+  int64_t objective;         /* O(out) */
+} mccref_stats;
+
+/* Mirkin distance between partitions a and b of n items: the number of
+ * ordered pairs (u, v), u != v, co-clustered in exactly one of them
+ * (Methods, "The consensus clustering problem"; Appendix, Eq. distance,
+ * counted over ordered pairs). */
+int mccref_mirkin(const int32_t* a, const int32_t* b, int64_t n, int64_t* result);
+
+/* O(C) = sum_i Mirkin(C, P_i)  (Eq. objective1 with the Mirkin distance). */
+int mccref_objective(const int32_t* c, const int32_t* labels, int32_t k, int64_t n,
+                     int64_t* result);
+
+/* Exact gain of moving v from C(v) to cluster `target` (Eq. objective3 with
+ * the u = v term left out), in unordered-pair units:
+ * O(after) - O(before) = 2 * result. */
+int mccref_delta(const int32_t* c, const int32_t* labels, int32_t k, int64_t n,
+                 int64_t v, int32_t target, int64_t* result);
+
+/* Best move of each vertex in [v_begin, v_end) against the frozen state c
+ * (Eq. objective4): best[j] = argmin over neighbour clusters of (gain, id),
+ * or -1 when v has no candidate; dbest[j] its gain (0 if none); ncand[j] the
+ * number of candidate clusters.  Arrays are indexed j = v - v_begin. */
+int mccref_score(const int64_t* row_ptr, const int32_t* col, int64_t n,
+                 const int32_t* labels, int32_t k, const int32_t* c,
+                 int64_t v_begin, int64_t v_end, int32_t literal_self_term,
+                 int32_t* best, int64_t* dbest, int32_t* ncand);
+
+/* The whole greedy consensus with synchronous rounds (Methods, "The
+ * algorithm" and "Parallel algorithm").  init: int32[n] in [0, n), used
+ * verbatim as cluster IDs, or NULL for singletons.  out: int32[n], may alias
+ * init.  trace: NULL or int64[max_rounds * 4] receiving per pass
+ * (accepted, committed, fallback, objective after the pass); the final
+ * pass that finds no move records (0, 0, 0, O). */
+int mccref_consensus(const int64_t* row_ptr, const int32_t* col, int64_t n,
+                     const int32_t* labels, int32_t k, const int32_t* init,
+                     int32_t* out, mccref_stats* stats, int64_t* trace);
+
+/* Relabel cluster ids in [0, n) to [0, clusters) in order of first occurrence. */
+int mccref_canonicalize(const int32_t* in, int32_t* out, int64_t n, int32_t* clusters);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
