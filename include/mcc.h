@@ -1,0 +1,163 @@
+/*
+ * libmcc: median consensus clustering on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "Parallel Algorithms for Median Consensus Clustering in Complex
+ * Networks" (Hussain, Halappanavar, Chatterjee, Radicchi, Fortunato, Azad).
+ * Given a graph and k partitions P_1..P_k of its vertices, find a consensus
+ * partition C minimising sum_i Mirkin(C, P_i) (Eq. objective1) by greedy
+ * local moves: each vertex may move into a cluster that holds one of its
+ * graph neighbours (Eq. objective4), scored by the exact change of the
+ * objective (Eq. objective3 without the vertex's pair with itself), all
+ * vertices scored against the partition as it stands at the start of a pass
+ * and the accepted moves applied together (Methods, "Parallel algorithm").
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (memory on the current HIP device,
+ *    e.g. a torch tensor's data_ptr), unless a comment says "host".  The
+ *    caller owns every buffer; the library keeps no pointer after a call
+ *    returns and allocates its own workspace on the given stream.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream.  Each call is stream-ordered and returns only once its results
+ *    are complete (it synchronises with the stream).
+ *  - Return value: 0 on success or a negative MCC_E* code.  No C++
+ *    exception crosses this interface.  On error, outputs are unspecified.
+ *  - Calls on different streams are independent; calls that share a stream
+ *    are serialised by it.
+ */
+#ifndef MCC_H
+#define MCC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes --------------------------------------------------------- */
+#define MCC_OK 0
+#define MCC_EINVAL (-1)   /* NULL pointer, k < 1, n < 0, n*k >= 2^31, a label < 0,
+                             an init id outside [0, n), bad sizes */
+#define MCC_EGRAPH (-2)   /* invalid CSR (only checked with MCC_F_VALIDATE) */
+#define MCC_ENOMEM (-3)   /* device allocation failed */
+#define MCC_EDEVICE (-4)  /* a HIP runtime call failed; see mcc_strerror */
+#define MCC_ENOTSUP (-5)  /* the instance needs a table larger than the library
+                             supports (see mcc_consensus) */
+
+/* ---- flags --------------------------------------------------------------- */
+#define MCC_F_VALIDATE 0x1u /* check the CSR on the device before solving */
+#define MCC_F_TRACE 0x2u    /* fill stats->trace (host array) per pass */
+#define MCC_F_LITERAL 0x4u  /* score with the paper's printed Eq. objective3,
+                               whose sum over u includes u = v and so adds k to
+                               every gain (an ablation; default is the exact
+                               gain) */
+
+/* CSR graph: row_ptr[n + 1] (int64, row_ptr[0] = 0, non-decreasing,
+ * row_ptr[n] = nnz) and col[nnz] (int32 vertex ids in [0, n)).  Arcs are
+ * read as out-neighbours; self-loops are ignored and repeated arcs are
+ * harmless.  Undirected graphs store both directions. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* row_ptr;
+  const int32_t* col;
+} mcc_csr;
+
+typedef struct {
+  /* in */
+  int32_t max_rounds; /* cap on scoring passes; 0 means 1000 */
+  uint32_t flags;     /* MCC_F_* */
+  void* stream;       /* hipStream_t or NULL */
+  int64_t* trace;     /* host int64[max_rounds * 4] when MCC_F_TRACE: per pass
+                         (accepted moves, committed moves, 1 if the pass fell
+                         back to the conflict-free subset, objective after
+                         the pass); the final pass that finds no move records
+                         (0, 0, 0, objective) */
+  int32_t lanes;      /* lanes that score one vertex: 0 = automatic, else one
+                         of 4, 8, 16, 32, 64 (a tuning knob; results do not
+                         depend on it) */
+  int32_t reserved;
+  /* out */
+  int32_t passes;          /* scoring passes, including the final one that
+                              finds no improving move */
+  int32_t converged;       /* 1 if stopped because no vertex can move */
+  int32_t fallback_rounds; /* passes whose full batch did not lower the
+                              objective */
+  int32_t clusters;        /* distinct clusters in the output */
+  int64_t moves;           /* committed vertex moves over all passes */
+  int64_t candidate_evals; /* sum over passes and vertices of the number of
+                              candidate clusters scored */
+  int64_t objective_init;  /* sum_i Mirkin(init, P_i) */
+  int64_t objective;       /* sum_i Mirkin(out, P_i) */
+  float ms_total;          /* wall time of the call on the stream */
+  float ms_passes;         /* time spent in the pass loop */
+} mcc_stats;
+
+/*
+ * Greedy median consensus (Methods, "The algorithm" and "Parallel
+ * algorithm").
+ *
+ *  g       CSR graph (host struct holding device pointers).
+ *  labels  HOST array of k device pointers; labels[i] is int32[n] holding
+ *          partition P_i (any label values >= 0).
+ *  k       number of input partitions, >= 1.
+ *  init    int32[n] initial consensus, ids in [0, n) used verbatim as cluster
+ *          ids (they are the tie-break keys), or NULL for singletons
+ *          (C(v) = v, the paper's initialisation).
+ *  out     int32[n] final consensus as cluster ids (a subset of the initial
+ *          ids, so passing it back as `init` resumes exactly).  May alias
+ *          init.
+ *  stats   host struct, may be NULL (then max_rounds = 1000, no flags, the
+ *          default stream).
+ *
+ * Per pass, with the partition frozen: every vertex v scores each cluster c'
+ * holding a neighbour (other than its own cluster c) by
+ *   gain = 2 (S_c(v) - S_c'(v)) + k (|c'| - |c| - 1),
+ *   S_x(v) = sum_i |{u in x : P_i(u) = P_i(v)}|,
+ * keeps the smallest (gain, cluster id) and proposes it if gain < 0.  If
+ * applying all proposals together lowers the objective they are committed;
+ * otherwise each cluster touched by a proposal is owned by its smallest
+ * (gain, vertex id) proposer and only proposals owning both of their clusters
+ * are committed.  The loop stops when no vertex proposes (converged = 1) or
+ * after max_rounds passes (converged = 0, not an error).
+ *
+ * The result (out and every stats field except the timings) is a
+ * deterministic function of the inputs and equals the plain sequential
+ * definition bit for bit.  Limits: n * k < 2^31; the contingency tables
+ * (consensus cluster x label, per partition) must fit the library's table
+ * budget, else MCC_ENOTSUP.
+ */
+int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k,
+                  const int32_t* init, int32_t* out, mcc_stats* stats);
+
+/*
+ * Objective of a given partition: *result (host) = sum_i Mirkin(c, P_i)
+ * (Eq. objective1), Mirkin counted over ordered pairs.  c: int32[n] ids in
+ * [0, n); labels as for mcc_consensus.
+ */
+int mcc_objective(const int32_t* c, const int32_t* const* labels, int32_t k, int64_t n,
+                  int64_t* result, void* stream);
+
+/*
+ * Mirkin distance (Methods, "The consensus clustering problem"; Appendix,
+ * Eq. distance): *result (host) = the number of ordered pairs (u, v), u != v,
+ * co-clustered in exactly one of a and b = sum |A|^2 + sum |B|^2
+ * - 2 sum |A n B|^2.  a, b: int32[n], any label values >= 0.
+ */
+int mcc_mirkin(const int32_t* a, const int32_t* b, int64_t n, int64_t* result, void* stream);
+
+/*
+ * Relabel cluster ids in [0, n) to [0, *clusters) in order of first
+ * occurrence (presentation labels for a consensus).  in, out: int32[n], may
+ * alias.  clusters: host, may be NULL.
+ */
+int mcc_canonicalize(const int32_t* in, int32_t* out, int64_t n, int32_t* clusters,
+                     void* stream);
+
+/* Static text for a return code (for MCC_EDEVICE, the last HIP error seen
+ * on this thread). */
+const char* mcc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

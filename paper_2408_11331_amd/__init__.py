@@ -1,0 +1,170 @@
+"""Python binding of libmcc (median consensus clustering on MI355X).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libmcc.so``; torch tensors provide device memory and streams.
+The library must be built (``paper_2408_11331_amd.build.build()``); nothing
+here falls back to another implementation when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmcc.so")
+
+MCC_OK, MCC_EINVAL, MCC_EGRAPH, MCC_ENOMEM, MCC_EDEVICE, MCC_ENOTSUP = 0, -1, -2, -3, -4, -5
+MCC_F_VALIDATE, MCC_F_TRACE, MCC_F_LITERAL = 0x1, 0x2, 0x4
+
+# every function include/mcc.h declares
+EXPORTS = ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize", "mcc_strerror")
+
+
+class Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("max_rounds", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("stream", ctypes.c_void_p), ("trace", ctypes.c_void_p),
+        ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("passes", ctypes.c_int32), ("converged", ctypes.c_int32),
+        ("fallback_rounds", ctypes.c_int32), ("clusters", ctypes.c_int32),
+        ("moves", ctypes.c_int64), ("candidate_evals", ctypes.c_int64),
+        ("objective_init", ctypes.c_int64), ("objective", ctypes.c_int64),
+        ("ms_total", ctypes.c_float), ("ms_passes", ctypes.c_float),
+    ]
+
+    OUT = ("passes", "converged", "fallback_rounds", "clusters", "moves", "candidate_evals",
+           "objective_init", "objective", "ms_total", "ms_passes")
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f in self.OUT}
+
+
+class MccError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmcc error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libmcc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2408_11331_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        p, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        L.mcc_consensus.argtypes = [ctypes.POINTER(Csr), p, i32, p, p, ctypes.POINTER(Stats)]
+        L.mcc_objective.argtypes = [p, p, i32, i64, p, p]
+        L.mcc_mirkin.argtypes = [p, p, i64, p, p]
+        L.mcc_canonicalize.argtypes = [p, p, i64, p, p]
+        L.mcc_strerror.argtypes = [ctypes.c_int]
+        L.mcc_strerror.restype = ctypes.c_char_p
+        for f in ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise MccError(rc, lib().mcc_strerror(rc).decode())
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_i32(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32:
+        raise TypeError(f"{name} must be a CUDA int32 tensor")
+    return t.contiguous()
+
+
+def _label_ptrs(labels):
+    """Labels as a (k, n) tensor or a sequence of n-vectors -> ctypes array."""
+    rows = [labels[i] for i in range(labels.shape[0])] if hasattr(labels, "shape") and \
+        labels.dim() == 2 else list(labels)
+    rows = [_dev_i32(r, "labels") for r in rows]
+    arr = (ctypes.c_void_p * max(1, len(rows)))(*[r.data_ptr() for r in rows])
+    return rows, arr
+
+
+def consensus(row_ptr, col, labels, init=None, *, max_rounds=0, flags=0, lanes=0,
+              stream=None, out=None, trace=False):
+    """Greedy median consensus on the GPU.
+
+    row_ptr: int64 CUDA tensor [n+1]; col: int32 CUDA tensor [nnz];
+    labels: int32 CUDA tensor [k, n] (or k tensors [n]); init: int32 [n] in
+    [0, n) or None (singletons).  Returns ``(out, stats)`` (and the per-pass
+    trace as a list of 4-tuples when ``trace``)."""
+    import torch
+    if row_ptr.dtype != torch.int64 or not row_ptr.is_cuda:
+        raise TypeError("row_ptr must be a CUDA int64 tensor")
+    row_ptr = row_ptr.contiguous()
+    col = _dev_i32(col, "col")
+    rows, arr = _label_ptrs(labels)
+    n = row_ptr.numel() - 1
+    if init is not None:
+        init = _dev_i32(init, "init")
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=row_ptr.device)
+    g = Csr(n, col.numel(), row_ptr.data_ptr(), col.data_ptr() if col.numel() else None)
+    st = Stats()
+    st.max_rounds = max_rounds
+    st.flags = flags | (MCC_F_TRACE if trace else 0)
+    st.stream = _stream_ptr(stream)
+    st.lanes = lanes
+    mr = max_rounds if max_rounds > 0 else 1000
+    tbuf = (ctypes.c_int64 * (4 * mr))() if trace else None
+    st.trace = ctypes.cast(tbuf, ctypes.c_void_p) if trace else None
+    _check(lib().mcc_consensus(ctypes.byref(g), arr, len(rows),
+                               init.data_ptr() if init is not None else None,
+                               out.data_ptr() if n > 0 else None, ctypes.byref(st)))
+    d = st.as_dict()
+    if trace:
+        tr = [tuple(tbuf[4 * j:4 * j + 4]) for j in range(d["passes"])]
+        return out, d, tr
+    return out, d
+
+
+def objective(c, labels, stream=None) -> int:
+    c = _dev_i32(c, "c")
+    rows, arr = _label_ptrs(labels)
+    res = ctypes.c_int64(0)
+    _check(lib().mcc_objective(c.data_ptr() if c.numel() else None, arr, len(rows), c.numel(),
+                               ctypes.byref(res), _stream_ptr(stream)))
+    return res.value
+
+
+def mirkin(a, b, stream=None) -> int:
+    a, b = _dev_i32(a, "a"), _dev_i32(b, "b")
+    if a.numel() != b.numel():
+        raise ValueError("a and b differ in length")
+    res = ctypes.c_int64(0)
+    _check(lib().mcc_mirkin(a.data_ptr() if a.numel() else None,
+                            b.data_ptr() if b.numel() else None, a.numel(),
+                            ctypes.byref(res), _stream_ptr(stream)))
+    return res.value
+
+
+def canonicalize(x, out=None, stream=None):
+    import torch
+    x = _dev_i32(x, "x")
+    if out is None:
+        out = torch.empty_like(x)
+    cl = ctypes.c_int32(0)
+    _check(lib().mcc_canonicalize(x.data_ptr() if x.numel() else None,
+                                  out.data_ptr() if x.numel() else None, x.numel(),
+                                  ctypes.byref(cl), _stream_ptr(stream)))
+    return out, cl.value

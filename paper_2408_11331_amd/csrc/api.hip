@@ -1,0 +1,528 @@
+// Host side of libmcc: argument checks, stream-ordered workspace, the setup
+// sequence and the device-driven pass loop behind the C interface in
+// include/mcc.h.
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "impl.h"
+#include "mcc.h"
+
+namespace mcc {
+// setup.hip
+void launch_dense_map(const int32_t* in, int64_t n, const int32_t* scan, int32_t* out,
+                      hipStream_t st);
+}
+
+namespace {
+
+using namespace mcc;
+
+thread_local std::string g_hip_error;
+
+// Largest label flag array (sum over partitions of max label + 1) and
+// largest dense table (sum over partitions of clusters x labels) accepted.
+constexpr int64_t kMaxLabelFlags = (int64_t)1 << 30;
+constexpr int64_t kMaxTableEntries = (int64_t)3 << 29;  // 6 GiB of int32 counts
+
+struct HipError {
+  hipError_t e;
+};
+
+inline void hipck(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    g_hip_error = std::string(what) + ": " + hipGetErrorString(e);
+    throw HipError{e};
+  }
+}
+#define HIPCK(x) hipck((x), #x)
+
+struct NoMem {};
+struct Status {
+  int code;
+};
+
+// Stream-ordered scratch allocations, released on the same stream when the
+// call returns (the pool keeps them warm for the next call).
+class Arena {
+ public:
+  explicit Arena(hipStream_t st) : st_(st) {}
+  ~Arena() {
+    // host staging buffers may still feed queued copies: drain first
+    (void)hipStreamSynchronize(st_);
+    for (void* p : ptrs_) (void)hipFreeAsync(p, st_);
+  }
+  // Host buffer that lives as long as the arena (source of async copies).
+  template <class T>
+  T* host(const std::vector<T>& src) {
+    staging_.emplace_back(src.size() * sizeof(T) + 1);
+    memcpy(staging_.back().data(), src.data(), src.size() * sizeof(T));
+    return reinterpret_cast<T*>(staging_.back().data());
+  }
+  template <class T>
+  T* get(int64_t count) {
+    if (count < 1) count = 1;
+    void* p = nullptr;
+    hipError_t e = hipMallocAsync(&p, (size_t)count * sizeof(T), st_);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      throw NoMem{};
+    }
+    hipck(e, "hipMallocAsync");
+    ptrs_.push_back(p);
+    return static_cast<T*>(p);
+  }
+
+ private:
+  hipStream_t st_;
+  std::vector<void*> ptrs_;
+  std::vector<std::vector<unsigned char>> staging_;
+};
+
+int device_sms() {
+  static thread_local int cached = 0;
+  if (!cached) {
+    int dev = 0, sms = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&sms, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        sms > 0)
+      cached = sms;
+    else
+      cached = 256;
+  }
+  return cached;
+}
+
+// True if p can be dereferenced by a kernel on the current device.
+bool device_visible(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t at;
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged ||
+         at.devicePointer != nullptr;
+}
+
+// Wait for the stream and surface any launch or execution error.
+void sync(hipStream_t st) {
+  HIPCK(hipStreamSynchronize(st));
+  HIPCK(hipGetLastError());
+}
+
+template <class T>
+void d2h(T* host, const T* dev, int64_t count, hipStream_t st) {
+  HIPCK(hipMemcpyAsync(host, dev, sizeof(T) * (size_t)count, hipMemcpyDeviceToHost, st));
+}
+template <class T>
+void h2d(T* dev, const T* host, int64_t count, hipStream_t st) {
+  HIPCK(hipMemcpyAsync(dev, host, sizeof(T) * (size_t)count, hipMemcpyHostToDevice, st));
+}
+
+// Dense relabelling of k partitions: scan[loff[i] + x] - scan[loff[i]] is
+// the id of label x of partition i, L[i] the number of distinct labels.
+struct Compacted {
+  const int32_t* const* dlabels = nullptr;
+  int64_t* loff = nullptr;  // device, k + 1
+  int32_t* scan = nullptr;  // device, loff[k] + 1
+  int32_t* L = nullptr;     // device, k
+  std::vector<int32_t> Lh;  // host copy
+};
+
+// Everything the passes need, built from the partitions and an initial
+// consensus.
+struct Solve {
+  int64_t n = 0;
+  int32_t k = 0;
+  int32_t K0 = 0;
+  Compacted lab;
+  int32_t* C = nullptr;
+  int32_t* rawid = nullptr;
+  int32_t* Lvm = nullptr;
+  int32_t* s = nullptr;
+  int64_t* toff = nullptr;
+  int32_t* N = nullptr;
+  int64_t total = 0;
+  int64_t* acc = nullptr;  // sum s^2, sum |P_il|^2, sum N^2
+};
+
+// Stage 1: label ranges, optional init-range and CSR checks.
+void compact_labels(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
+                    Compacted* out, int32_t* err_dev, hipStream_t st, int32_t* host_err,
+                    std::vector<int32_t>* maxlab_host) {
+  const int32_t k = (int32_t)hptrs.size();
+  const int32_t** dl = ar.get<const int32_t*>(k);
+  h2d(dl, ar.host(hptrs), k, st);
+  int32_t* maxlab = ar.get<int32_t>(k);
+  launch_fill_i32(maxlab, k, -1, st);
+  launch_label_max(dl, k, n, maxlab, err_dev, st);
+  maxlab_host->assign(k, -1);
+  d2h(maxlab_host->data(), maxlab, k, st);
+  d2h(host_err, err_dev, 1, st);
+  out->dlabels = dl;
+}
+
+void compact_labels_finish(Arena& ar, int64_t n, int32_t k, const std::vector<int32_t>& maxlab,
+                           Compacted* out, hipStream_t st) {
+  std::vector<int64_t> loff(k + 1, 0);
+  for (int i = 0; i < k; ++i) loff[i + 1] = loff[i] + (int64_t)maxlab[i] + 1;
+  if (loff[k] > kMaxLabelFlags) throw Status{MCC_ENOTSUP};
+  out->loff = ar.get<int64_t>(k + 1);
+  h2d(out->loff, ar.host(loff), k + 1, st);
+  int32_t* flags = ar.get<int32_t>(loff[k] + 1);
+  launch_fill_i32(flags, loff[k] + 1, 0, st);
+  launch_label_mark(out->dlabels, k, n, out->loff, flags, st);
+  out->scan = ar.get<int32_t>(loff[k] + 1);
+  int32_t* tmp = ar.get<int32_t>(scan_tmp_elems(loff[k]));
+  launch_scan(flags, out->scan, loff[k], tmp, st);
+  out->L = ar.get<int32_t>(k);
+  launch_label_counts(out->scan, out->loff, k, out->L, st);
+}
+
+// The full setup: compaction of labels and clusters, tables, initial
+// objective.  `init` null means singletons.  `want_rows` builds the
+// vertex-major label rows the passes read.
+void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
+                 const int32_t* init, bool want_rows, const mcc_csr* g_validate, Solve* S,
+                 hipStream_t st) {
+  const int32_t k = (int32_t)hptrs.size();
+  S->n = n;
+  S->k = k;
+  int32_t* err = ar.get<int32_t>(1);
+  launch_fill_i32(err, 1, 0, st);
+  int32_t* cflags = nullptr;
+  if (init) {
+    cflags = ar.get<int32_t>(n + 1);
+    launch_fill_i32(cflags, n + 1, 0, st);
+    launch_cluster_mark(init, n, cflags, err, st);
+  }
+  if (g_validate)
+    launch_validate_csr(g_validate->row_ptr, g_validate->col, n, g_validate->nnz, err, st);
+  int32_t herr = 0;
+  std::vector<int32_t> maxlab;
+  compact_labels(ar, hptrs, n, &S->lab, err, st, &herr, &maxlab);
+  sync(st);
+  if (herr & kErrGraph) throw Status{MCC_EGRAPH};
+  if (herr & (kErrNegLabel | kErrInitRange)) throw Status{MCC_EINVAL};
+  compact_labels_finish(ar, n, k, maxlab, &S->lab, st);
+  int32_t* cmap = nullptr;
+  if (init) {
+    cmap = ar.get<int32_t>(n + 1);
+    int32_t* tmp = ar.get<int32_t>(scan_tmp_elems(n));
+    launch_scan(cflags, cmap, n, tmp, st);
+  }
+  S->lab.Lh.assign(k, 0);
+  d2h(S->lab.Lh.data(), S->lab.L, k, st);
+  int32_t K0 = (int32_t)n;
+  if (init) d2h(&K0, cmap + n, 1, st);
+  sync(st);
+  S->K0 = K0;
+
+  std::vector<int64_t> toff(k + 1, 0);
+  for (int i = 0; i < k; ++i) toff[i + 1] = toff[i] + (int64_t)K0 * S->lab.Lh[i];
+  S->total = toff[k];
+  if (S->total > kMaxTableEntries) throw Status{MCC_ENOTSUP};
+  S->toff = ar.get<int64_t>(k + 1);
+  h2d(S->toff, ar.host(toff), k + 1, st);
+
+  S->C = ar.get<int32_t>(n);
+  S->rawid = ar.get<int32_t>(K0);
+  if (init) {
+    launch_cluster_assign(init, n, cmap, S->C, S->rawid, st);
+  } else {
+    launch_iota(S->C, n, st);
+    launch_iota(S->rawid, n, st);
+  }
+  if (want_rows) {
+    S->Lvm = ar.get<int32_t>(n * k);
+    launch_label_transpose(S->lab.dlabels, k, n, S->lab.loff, S->lab.scan, S->Lvm, st);
+  }
+  S->N = ar.get<int32_t>(S->total);
+  launch_fill_i32(S->N, S->total, 0, st);
+  S->s = ar.get<int32_t>(K0);
+  launch_fill_i32(S->s, K0, 0, st);
+  Tables t{S->N, S->toff, S->lab.L};
+  launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.scan, n, k, K0, t, S->s, st);
+  S->acc = ar.get<int64_t>(3);
+  launch_fill_u64(reinterpret_cast<uint64_t*>(S->acc), 3, 0ull, st);
+  launch_objective0(t, k, K0, S->s, S->total, S->acc, st);
+}
+
+int translate(const std::exception_ptr& ep) {
+  try {
+    std::rethrow_exception(ep);
+  } catch (const Status& s) {
+    return s.code;
+  } catch (const NoMem&) {
+    return MCC_ENOMEM;
+  } catch (const HipError&) {
+    return MCC_EDEVICE;
+  } catch (...) {
+    g_hip_error = "unexpected host exception";
+    return MCC_EDEVICE;
+  }
+}
+
+bool labels_ok(const int32_t* const* labels, int32_t k) {
+  if (!labels) return false;
+  for (int i = 0; i < k; ++i)
+    if (!device_visible(labels[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mcc_strerror(int code) {
+  switch (code) {
+    case MCC_OK: return "success";
+    case MCC_EINVAL: return "invalid argument";
+    case MCC_EGRAPH: return "invalid CSR graph";
+    case MCC_ENOMEM: return "out of device memory";
+    case MCC_EDEVICE: return g_hip_error.empty() ? "HIP runtime error" : g_hip_error.c_str();
+    case MCC_ENOTSUP: return "instance exceeds the supported table size";
+    default: return "unknown error code";
+  }
+}
+
+int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, const int32_t* init,
+                  int32_t* out, mcc_stats* stats) {
+  if (!g || k < 1 || g->n < 0 || g->nnz < 0) return MCC_EINVAL;
+  const int64_t n = g->n;
+  const int32_t max_rounds = stats && stats->max_rounds > 0 ? stats->max_rounds : 1000;
+  const uint32_t flags = stats ? stats->flags : 0u;
+  const int lanes_req = stats ? stats->lanes : 0;
+  if (stats && stats->max_rounds < 0) return MCC_EINVAL;
+  if (lanes_req != 0 && !score_lanes_ok(lanes_req)) return MCC_EINVAL;
+  if ((flags & MCC_F_TRACE) && !stats->trace) return MCC_EINVAL;
+  if ((int64_t)k * n >= ((int64_t)1 << 31)) return MCC_EINVAL;
+  if (!labels) return MCC_EINVAL;
+  if (stats) {
+    stats->passes = stats->converged = stats->fallback_rounds = stats->clusters = 0;
+    stats->moves = stats->candidate_evals = stats->objective_init = stats->objective = 0;
+    stats->ms_total = stats->ms_passes = 0.f;
+  }
+  if (n == 0) {
+    if (stats) {
+      stats->passes = 1;
+      stats->converged = 1;
+      if (flags & MCC_F_TRACE) memset(stats->trace, 0, 4 * sizeof(int64_t));
+    }
+    return MCC_OK;
+  }
+  if (!device_visible(g->row_ptr) || (g->nnz > 0 && !device_visible(g->col)) ||
+      !device_visible(out) || (init && !device_visible(init)) || !labels_ok(labels, k))
+    return MCC_EINVAL;
+
+  hipStream_t st = stats ? (hipStream_t)stats->stream : nullptr;
+  try {
+    Arena ar(st);
+    hipEvent_t e0, e1, e2, e3;
+    HIPCK(hipEventCreate(&e0));
+    HIPCK(hipEventCreate(&e1));
+    HIPCK(hipEventCreate(&e2));
+    HIPCK(hipEventCreate(&e3));
+    struct Ev {
+      hipEvent_t* e;
+      ~Ev() {
+        for (int j = 0; j < 4; ++j) (void)hipEventDestroy(e[j]);
+      }
+    };
+    hipEvent_t evs[4] = {e0, e1, e2, e3};
+    Ev guard{evs};
+    HIPCK(hipEventRecord(e0, st));
+
+    std::vector<const int32_t*> hptrs(labels, labels + k);
+    Solve S;
+    build_solve(ar, hptrs, n, init, true, (flags & MCC_F_VALIDATE) ? g : nullptr, &S, st);
+
+    int64_t* dtrace = nullptr;
+    if (flags & MCC_F_TRACE) dtrace = ar.get<int64_t>((int64_t)max_rounds * 4);
+    Ctl* ctl = ar.get<Ctl>(1);
+    launch_ctl_init(ctl, S.acc, k, max_rounds, dtrace, st);
+    uint64_t* owner = ar.get<uint64_t>(S.K0);
+    launch_fill_u64(owner, S.K0, ~0ull, st);
+    int32_t* prop = ar.get<int32_t>(n);
+    int64_t* dprop = ar.get<int64_t>(n);
+
+    PassArgs a;
+    a.ctl = ctl;
+    a.n = n;
+    a.k = k;
+    a.literal = (flags & MCC_F_LITERAL) ? 1 : 0;
+    a.row_ptr = g->row_ptr;
+    a.col = g->col;
+    a.C = S.C;
+    a.Lvm = S.Lvm;
+    a.t = Tables{S.N, S.toff, S.lab.L};
+    a.s = S.s;
+    a.prop = prop;
+    a.dprop = dprop;
+    a.owner = owner;
+
+    const int lanes = lanes_req ? lanes_req : score_lanes_auto(k);
+    const int sms = device_sms();
+    const int64_t groups_needed = (n * lanes + kBlock - 1) / kBlock;
+    const int grid_score = (int)std::max<int64_t>(1, std::min<int64_t>(groups_needed, sms * 8));
+    const int grid_apply =
+        (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, sms * 4));
+
+    HIPCK(hipEventRecord(e1, st));
+    Ctl hc;
+    memset(&hc, 0, sizeof hc);
+    int enqueued = 0, chunk = 2;
+    while (enqueued < max_rounds) {
+      const int todo = std::min(chunk, max_rounds - enqueued);
+      for (int j = 0; j < todo; ++j) enqueue_pass(a, lanes, grid_score, grid_apply, st);
+      enqueued += todo;
+      d2h(&hc, ctl, 1, st);
+      sync(st);
+      if (hc.done) break;
+      chunk = std::min(chunk * 2, 16);
+    }
+    HIPCK(hipEventRecord(e2, st));
+
+    launch_finish(S.C, S.rawid, n, out, st);
+    int32_t* ncl = ar.get<int32_t>(1);
+    launch_fill_i32(ncl, 1, 0, st);
+    launch_count_nonzero(S.s, S.K0, ncl, st);
+    int32_t clusters = 0;
+    d2h(&clusters, ncl, 1, st);
+    d2h(&hc, ctl, 1, st);
+    int64_t acc[3];
+    d2h(acc, S.acc, 3, st);
+    HIPCK(hipEventRecord(e3, st));
+    sync(st);
+    if (flags & MCC_F_TRACE) {
+      memset(stats->trace, 0, sizeof(int64_t) * 4 * (size_t)max_rounds);
+      d2h(stats->trace, dtrace, (int64_t)4 * hc.passes, st);
+      sync(st);
+    }
+    if (stats) {
+      stats->passes = hc.passes;
+      stats->converged = hc.converged;
+      stats->fallback_rounds = hc.fallback_rounds;
+      stats->clusters = clusters;
+      stats->moves = hc.moves;
+      stats->candidate_evals = hc.evals;
+      stats->objective_init = (int64_t)k * acc[0] + acc[1] - 2 * acc[2];
+      stats->objective = hc.O;
+      float ms = 0.f;
+      HIPCK(hipEventElapsedTime(&ms, e0, e3));
+      stats->ms_total = ms;
+      HIPCK(hipEventElapsedTime(&ms, e1, e2));
+      stats->ms_passes = ms;
+    }
+    return MCC_OK;
+  } catch (...) {
+    return translate(std::current_exception());
+  }
+}
+
+int mcc_objective(const int32_t* c, const int32_t* const* labels, int32_t k, int64_t n,
+                  int64_t* result, void* stream) {
+  if (!result || k < 1 || n < 0) return MCC_EINVAL;
+  if ((int64_t)k * n >= ((int64_t)1 << 31)) return MCC_EINVAL;
+  if (n == 0) {
+    *result = 0;
+    return MCC_OK;
+  }
+  if (!device_visible(c) || !labels_ok(labels, k)) return MCC_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    Arena ar(st);
+    std::vector<const int32_t*> hptrs(labels, labels + k);
+    Solve S;
+    build_solve(ar, hptrs, n, c, false, nullptr, &S, st);
+    int64_t acc[3];
+    d2h(acc, S.acc, 3, st);
+    sync(st);
+    *result = (int64_t)k * acc[0] + acc[1] - 2 * acc[2];
+    return MCC_OK;
+  } catch (...) {
+    return translate(std::current_exception());
+  }
+}
+
+int mcc_mirkin(const int32_t* a, const int32_t* b, int64_t n, int64_t* result, void* stream) {
+  if (!result || n < 0 || n >= ((int64_t)1 << 31)) return MCC_EINVAL;
+  if (n == 0) {
+    *result = 0;
+    return MCC_OK;
+  }
+  if (!device_visible(a) || !device_visible(b)) return MCC_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    Arena ar(st);
+    // dense ids of a (in [0, n)) serve as the consensus, b as the single
+    // partition: the objective with k = 1 is Mirkin(a, b)
+    std::vector<const int32_t*> pa{a};
+    Compacted ca;
+    int32_t* err = ar.get<int32_t>(1);
+    launch_fill_i32(err, 1, 0, st);
+    int32_t herr = 0;
+    std::vector<int32_t> maxlab;
+    compact_labels(ar, pa, n, &ca, err, st, &herr, &maxlab);
+    sync(st);
+    if (herr & kErrNegLabel) return MCC_EINVAL;
+    compact_labels_finish(ar, n, 1, maxlab, &ca, st);
+    int32_t* da = ar.get<int32_t>(n);
+    launch_dense_map(a, n, ca.scan, da, st);
+    std::vector<const int32_t*> pb{b};
+    Solve S;
+    build_solve(ar, pb, n, da, false, nullptr, &S, st);
+    int64_t acc[3];
+    d2h(acc, S.acc, 3, st);
+    sync(st);
+    *result = acc[0] + acc[1] - 2 * acc[2];
+    return MCC_OK;
+  } catch (...) {
+    return translate(std::current_exception());
+  }
+}
+
+int mcc_canonicalize(const int32_t* in, int32_t* out, int64_t n, int32_t* clusters,
+                     void* stream) {
+  if (n < 0 || n >= ((int64_t)1 << 31)) return MCC_EINVAL;
+  if (n == 0) {
+    if (clusters) *clusters = 0;
+    return MCC_OK;
+  }
+  if (!device_visible(in) || !device_visible(out)) return MCC_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    Arena ar(st);
+    int32_t* err = ar.get<int32_t>(1);
+    launch_fill_i32(err, 1, 0, st);
+    int32_t* cflags = ar.get<int32_t>(n + 1);
+    launch_fill_i32(cflags, n + 1, 0, st);
+    launch_cluster_mark(in, n, cflags, err, st);  // range check
+    int32_t herr = 0;
+    d2h(&herr, err, 1, st);
+    sync(st);
+    if (herr) return MCC_EINVAL;
+    int32_t* first = ar.get<int32_t>(n);
+    launch_fill_i32(first, n, 0x7fffffff, st);
+    launch_first_occurrence(in, n, first, st);
+    int32_t* fl = ar.get<int32_t>(n + 1);
+    launch_first_flags(in, n, first, fl, st);
+    int32_t* rank = ar.get<int32_t>(n + 1);
+    int32_t* tmp = ar.get<int32_t>(scan_tmp_elems(n));
+    launch_scan(fl, rank, n, tmp, st);
+    launch_canonical_write(in, n, first, rank, out, st);
+    int32_t total = 0;
+    d2h(&total, rank + n, 1, st);
+    sync(st);
+    if (clusters) *clusters = total;
+    return MCC_OK;
+  } catch (...) {
+    return translate(std::current_exception());
+  }
+}
+
+}  // extern "C"

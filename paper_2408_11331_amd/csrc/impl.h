@@ -1,0 +1,109 @@
+// Internal declarations shared by the kernels and the host driver of libmcc.
+// Not part of the public interface (include/mcc.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcc {
+
+constexpr int kBlock = 256;  // threads per workgroup for every kernel here
+
+// Device-resident control block of one solve.  The pass loop is driven from
+// the device: every kernel of a pass reads `done` first and returns at once
+// when the solve has finished, so the host can enqueue several passes
+// without waiting for each.
+struct Ctl {
+  int32_t done;             // 1 once no further pass may run
+  int32_t fallback;         // 1 if the current pass commits only a subset
+  int32_t nprop;            // proposals of the current pass
+  int32_t committed;        // moves committed by the current fallback pass
+  int32_t passes;           // scoring passes run
+  int32_t converged;        // 1 when a pass finds no proposal
+  int32_t fallback_rounds;  // passes that fell back
+  int32_t max_rounds;       // pass cap
+  int32_t k;                // number of input partitions
+  int32_t err;              // input error bits (see kErr*)
+  int64_t pass_evals;       // candidate clusters scored in the current pass
+  int64_t evals;            // candidate clusters scored in all passes
+  int64_t dS2;              // change of sum_c s_c^2 caused by tracked updates
+  int64_t dN2;              // change of sum_i sum_(c,l) N_i(c,l)^2, same
+  int64_t O;                // current objective sum_i Mirkin(C, P_i)
+  int64_t moves;            // committed moves in all passes
+  int64_t* trace;           // device int64[max_rounds * 4] or null
+};
+
+constexpr int32_t kErrNegLabel = 1;
+constexpr int32_t kErrInitRange = 2;
+constexpr int32_t kErrGraph = 4;
+
+// Dense contingency tables: for partition i, the count of vertices of
+// consensus cluster x (dense index) whose dense label in P_i is l sits at
+// N[toff[i] + x * L[i] + l].
+struct Tables {
+  int32_t* N;
+  const int64_t* toff;
+  const int32_t* L;
+};
+
+// ---- setup kernels (setup.hip) -------------------------------------------
+void launch_label_max(const int32_t* const* dlabels, int32_t k, int64_t n, int32_t* maxlab,
+                      int32_t* err, hipStream_t st);
+void launch_label_mark(const int32_t* const* dlabels, int32_t k, int64_t n,
+                       const int64_t* loff, int32_t* flags, hipStream_t st);
+void launch_scan(const int32_t* in, int32_t* out, int64_t len, int32_t* tmp, hipStream_t st);
+int64_t scan_tmp_elems(int64_t len);
+void launch_label_counts(const int32_t* scan, const int64_t* loff, int32_t k, int32_t* Lc,
+                         hipStream_t st);
+void launch_label_transpose(const int32_t* const* dlabels, int32_t k, int64_t n,
+                            const int64_t* loff, const int32_t* scan, int32_t* Lvm,
+                            hipStream_t st);
+void launch_cluster_mark(const int32_t* init, int64_t n, int32_t* flags, int32_t* err,
+                         hipStream_t st);
+void launch_cluster_assign(const int32_t* init, int64_t n, const int32_t* cmap, int32_t* C,
+                           int32_t* rawid, hipStream_t st);
+void launch_iota(int32_t* a, int64_t n, hipStream_t st);
+void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st);
+void launch_fill_u64(uint64_t* a, int64_t n, uint64_t v, hipStream_t st);
+void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t* loff,
+                  const int32_t* scan, int64_t n, int32_t k, int32_t K0, Tables t, int32_t* s,
+                  hipStream_t st);
+void launch_objective0(const Tables& t, int32_t k, int32_t K0, const int32_t* s,
+                       int64_t total_entries,
+                       int64_t* acc /* 3 int64: sum s^2, sum hist^2, sum N^2 */,
+                       hipStream_t st);
+void launch_validate_csr(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
+                         int32_t* err, hipStream_t st);
+void launch_finish(const int32_t* C, const int32_t* rawid, int64_t n, int32_t* out,
+                   hipStream_t st);
+void launch_count_nonzero(const int32_t* a, int64_t n, int32_t* count, hipStream_t st);
+void launch_first_occurrence(const int32_t* in, int64_t n, int32_t* first, hipStream_t st);
+void launch_first_flags(const int32_t* in, int64_t n, const int32_t* first, int32_t* flags,
+                        hipStream_t st);
+void launch_canonical_write(const int32_t* in, int64_t n, const int32_t* first,
+                            const int32_t* rank, int32_t* out, hipStream_t st);
+
+// ---- pass kernels (pass.hip) ----------------------------------------------
+struct PassArgs {
+  Ctl* ctl;
+  int64_t n;
+  int32_t k;
+  int32_t literal;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  int32_t* C;
+  const int32_t* Lvm;
+  Tables t;
+  int32_t* s;
+  int32_t* prop;      // proposed target cluster, -1 none; fallback marks
+  int64_t* dprop;     // gain of the proposal
+  uint64_t* owner;    // per cluster, fallback owners
+};
+
+int score_lanes_auto(int32_t k);
+bool score_lanes_ok(int lanes);
+void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, hipStream_t st);
+void launch_ctl_init(Ctl* ctl, const int64_t* acc, int32_t k, int32_t max_rounds,
+                     int64_t* trace, hipStream_t st);
+
+}  // namespace mcc

@@ -1,0 +1,397 @@
+// One synchronous pass of the greedy consensus (Methods, "Graph-aware
+// consensus clustering" and "Parallel algorithm"):
+//
+//   score      every vertex, against the frozen partition, finds the
+//              neighbour cluster with the smallest (gain, cluster id) and
+//              proposes it when the gain is negative (Eq. objective3/4)
+//   begin      count the pass; stop if nothing was proposed
+//   apply      apply every proposal to sizes and counts, measuring the exact
+//              change of the objective on the way
+//   decide     keep the batch if the objective dropped, else fall back
+//   commit     write the new cluster ids, or (fallback) undo the batch and
+//              elect an owner per touched cluster
+//   fb_commit  (fallback) apply the proposals that own both their clusters
+//   fb_finish  (fallback) release owners, write the committed cluster ids
+//   end        account the pass, enforce the pass cap
+//
+// Every kernel returns at once when the control block says the solve is
+// done, so the host may enqueue passes ahead of the device.
+//
+// Gain of moving v from c to x (exact, the pair (v, v) left out):
+//   2 (S_c(v) - S_x(v)) + k (s_x - s_c - 1),  S_y(v) = sum_i N_i(y, P_i(v)),
+// obtained from Eq. objective3 by summing (k - 2 delta_uv) over the members
+// of a cluster: delta_uv = k - #partitions agreeing on u, v, so the sum over
+// y is 2 S_y(v) - k s_y.
+//
+// Objective bookkeeping: O = k sum_x s_x^2 + sum_i sum_l |P_i l|^2
+// - 2 sum_i sum_(x,l) N_i(x,l)^2.  Each +-1 atomic update of a counter that
+// returns the previous value `old` changes that counter's square by
+// 2 old d + 1; summed over all updates of a pass this telescopes to the
+// exact change of the sum of squares whatever order the atomics land in, so
+// the batch's objective change is exact and deterministic.
+#include "impl.h"
+
+namespace mcc {
+
+namespace {
+
+constexpr int32_t kNone = -1;
+constexpr int64_t kGainBias = (int64_t)1 << 33;
+
+__device__ inline uint64_t owner_key(int64_t gain, int64_t v) {
+  // (gain, vertex) ordered lexicographically; gain lies in (-2^33, 0) and
+  // v in [0, 2^31)
+  return ((uint64_t)(gain + kGainBias) << 31) | (uint64_t)v;
+}
+
+template <int G>
+__device__ inline int32_t group_min(int32_t x) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, G));
+  return x;
+}
+
+template <int G>
+__device__ inline int32_t group_sum(int32_t x) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, G);
+  return x;
+}
+
+__device__ inline int64_t wave_sum64(int64_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ inline int32_t wave_sum32(int32_t x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// score: G lanes per vertex.  A lane keeps R neighbour cluster ids and the
+// labels of up to KR partitions in registers; larger degrees or k fall back
+// to re-reading memory.  Candidates are enumerated in increasing id by
+// repeated group minima, so duplicates vanish and ties resolve to the
+// smallest id without any sort.
+// ---------------------------------------------------------------------------
+constexpr int KR = 4;
+
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
+  if (a.ctl->done) return;
+  constexpr int R = (128 / G) > 1 ? (128 / G) : 1;
+  constexpr int32_t kInf = 0x7fffffff;
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t group = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  const int64_t ngroups = ((int64_t)gridDim.x * kBlock) / G;
+  const int32_t k = a.k;
+  const bool kfits = k <= KR * G;
+
+  int64_t toff[KR];
+  int32_t Lp[KR];
+#pragma unroll
+  for (int t = 0; t < KR; ++t) {
+    int i = lane + t * G;
+    toff[t] = i < k ? a.t.toff[i] : 0;
+    Lp[t] = i < k ? a.t.L[i] : 0;
+  }
+
+  int64_t evals = 0;
+  int32_t nprop = 0;
+  for (int64_t v = group; v < a.n; v += ngroups) {
+    const int32_t cv = a.C[v];
+    const int64_t beg = a.row_ptr[v], end = a.row_ptr[v + 1];
+    const bool fits = end - beg <= (int64_t)G * R;
+    int32_t x[R];
+    if (fits) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        int64_t j = beg + r * G + lane;
+        x[r] = kInf;
+        if (j < end) {
+          int32_t u = a.col[j];
+          int32_t cu = a.C[u];
+          if (u != v && cu != cv) x[r] = cu;
+        }
+      }
+    }
+    const int32_t* row = a.Lvm + v * k;
+    int32_t lab[KR];
+    if (kfits) {
+#pragma unroll
+      for (int t = 0; t < KR; ++t) {
+        int i = lane + t * G;
+        lab[t] = i < k ? row[i] : 0;
+      }
+    }
+    // S_y(v) summed over the group's lanes
+    auto agree = [&](int32_t y) -> int32_t {
+      int32_t sum = 0;
+      if (kfits) {
+#pragma unroll
+        for (int t = 0; t < KR; ++t) {
+          int i = lane + t * G;
+          if (i < k) sum += a.t.N[toff[t] + (int64_t)y * Lp[t] + lab[t]];
+        }
+      } else {
+        for (int i = lane; i < k; i += G)
+          sum += a.t.N[a.t.toff[i] + (int64_t)y * a.t.L[i] + row[i]];
+      }
+      return group_sum<G>(sum);
+    };
+
+    int32_t last = -1, ncand = 0, bestx = kNone;
+    int64_t bestd = 0, s_own = -1;
+    const int64_t sc = a.s[cv];
+    for (;;) {
+      int32_t m = kInf;
+      if (fits) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) m = min(m, x[r]);
+      } else {
+        for (int64_t j = beg + lane; j < end; j += G) {
+          int32_t u = a.col[j];
+          if (u == v) continue;
+          int32_t cu = a.C[u];
+          if (cu != cv && cu > last && cu < m) m = cu;
+        }
+      }
+      m = group_min<G>(m);
+      if (m == kInf) break;
+      if (s_own < 0) s_own = agree(cv);
+      const int64_t sx = agree(m);
+      int64_t d = 2 * (s_own - sx) + (int64_t)k * ((int64_t)a.s[m] - sc - 1);
+      if (a.literal) d += k;
+      if (ncand == 0 || d < bestd) {
+        bestd = d;
+        bestx = m;
+      }
+      ++ncand;
+      last = m;
+      if (fits) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (x[r] == m) x[r] = kInf;
+      }
+    }
+    if (lane == 0) {
+      evals += ncand;
+      const bool p = ncand > 0 && bestd < 0;
+      a.prop[v] = p ? bestx : kNone;
+      if (p) {
+        a.dprop[v] = bestd;
+        ++nprop;
+      }
+    }
+  }
+  evals = wave_sum64(evals);
+  nprop = wave_sum32(nprop);
+  if ((threadIdx.x & 63) == 0) {
+    if (evals) atomicAdd((unsigned long long*)&a.ctl->pass_evals, (unsigned long long)evals);
+    if (nprop) atomicAdd(&a.ctl->nprop, nprop);
+  }
+}
+
+__global__ void k_begin(Ctl* ctl) {
+  if (ctl->done) return;
+  ctl->passes += 1;
+  ctl->evals += ctl->pass_evals;
+  ctl->pass_evals = 0;
+  ctl->dS2 = 0;
+  ctl->dN2 = 0;
+  if (ctl->nprop == 0) {
+    ctl->converged = 1;
+    ctl->done = 1;
+    if (ctl->trace) {
+      int64_t* r = ctl->trace + (int64_t)(ctl->passes - 1) * 4;
+      r[0] = 0; r[1] = 0; r[2] = 0; r[3] = ctl->O;
+    }
+  }
+}
+
+// Apply the move of v (from -> to) with sign d (+1 apply, -1 undo) to the
+// sizes and counts; lanes of the wave take the partitions.  Returns this
+// lane's share of the change of the sums of squares (N part; the size part
+// is added by lane 0 to *ds2).
+__device__ inline int64_t move_counts(const PassArgs& a, int64_t v, int32_t from, int32_t to,
+                                      int32_t d, int lane, int64_t* ds2) {
+  int64_t acc = 0;
+  const int32_t* row = a.Lvm + v * a.k;
+  for (int i = lane; i < a.k; i += 64) {
+    const int64_t off = a.t.toff[i];
+    const int32_t Li = a.t.L[i];
+    const int32_t l = row[i];
+    int32_t o1 = atomicAdd(&a.t.N[off + (int64_t)to * Li + l], d);
+    int32_t o2 = atomicAdd(&a.t.N[off + (int64_t)from * Li + l], -d);
+    acc += 2 * (int64_t)o1 * d + 1 - 2 * (int64_t)o2 * d + 1;
+  }
+  if (lane == 0) {
+    int32_t o1 = atomicAdd(&a.s[to], d);
+    int32_t o2 = atomicAdd(&a.s[from], -d);
+    *ds2 += 2 * (int64_t)o1 * d + 1 - 2 * (int64_t)o2 * d + 1;
+  }
+  return acc;
+}
+
+// The apply-type kernels walk the vertices 64 at a time per wave: one
+// coalesced load of the proposals, a ballot, then the wave serves each
+// selected vertex with its lanes spread over the partitions.
+enum ApplyMode { kApplyAll = 0, kCommitOrElect = 1, kFallbackCommit = 2, kFallbackFinish = 3 };
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_apply(PassArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  if ((MODE == kFallbackCommit || MODE == kFallbackFinish) && !ctl->fallback) return;
+  const bool fb = ctl->fallback;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 64;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) / 64;
+  int64_t dn2 = 0, ds2 = 0;
+  int32_t committed = 0;
+  for (int64_t v0 = wave * 64; v0 < a.n; v0 += nwaves * 64) {
+    const int64_t v = v0 + lane;
+    int32_t p = v < a.n ? a.prop[v] : kNone;
+    bool sel;
+    if (MODE == kFallbackFinish) sel = p != kNone;  // committed (>= 0) or not (<= -2)
+    else sel = p >= 0;
+    uint64_t mask = __ballot(sel);
+    while (mask) {
+      const int b = __ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      const int64_t w = v0 + b;
+      const int32_t pw = __shfl(p, b, 64);
+      const int32_t from = a.C[w];
+      if (MODE == kApplyAll) {
+        dn2 += move_counts(a, w, from, pw, +1, lane, &ds2);
+      } else if (MODE == kCommitOrElect) {
+        if (!fb) {
+          if (lane == 0) a.C[w] = pw;
+        } else {
+          move_counts(a, w, from, pw, -1, lane, &ds2);  // undo the batch
+          if (lane == 0) {
+            const uint64_t key = owner_key(a.dprop[w], w);
+            atomicMin((unsigned long long*)&a.owner[from], (unsigned long long)key);
+            atomicMin((unsigned long long*)&a.owner[pw], (unsigned long long)key);
+          }
+        }
+      } else if (MODE == kFallbackCommit) {
+        const uint64_t key = owner_key(a.dprop[w], w);
+        const bool own = a.owner[from] == key && a.owner[pw] == key;
+        if (own) {
+          dn2 += move_counts(a, w, from, pw, +1, lane, &ds2);
+          if (lane == 0) ++committed;
+        } else if (lane == 0) {
+          a.prop[w] = -2 - pw;  // proposal kept out of this pass
+        }
+      } else {  // kFallbackFinish
+        const int32_t to = pw >= 0 ? pw : -2 - pw;
+        if (lane == 0) {
+          a.owner[from] = ~0ull;
+          a.owner[to] = ~0ull;
+          if (pw >= 0) a.C[w] = pw;
+        }
+      }
+    }
+  }
+  if (MODE == kApplyAll || MODE == kFallbackCommit) {
+    dn2 = wave_sum64(dn2);
+    ds2 = wave_sum64(ds2);
+    committed = wave_sum32(committed);
+    if (lane == 0) {
+      if (dn2) atomicAdd((unsigned long long*)&ctl->dN2, (unsigned long long)dn2);
+      if (ds2) atomicAdd((unsigned long long*)&ctl->dS2, (unsigned long long)ds2);
+      if (committed) atomicAdd(&ctl->committed, committed);
+    }
+  }
+}
+
+__global__ void k_decide(Ctl* ctl) {
+  if (ctl->done) return;
+  const int64_t dO = (int64_t)ctl->k * ctl->dS2 - 2 * ctl->dN2;
+  ctl->dS2 = 0;
+  ctl->dN2 = 0;
+  if (dO < 0) {
+    ctl->fallback = 0;
+    ctl->O += dO;
+    ctl->committed = ctl->nprop;
+  } else {
+    ctl->fallback = 1;
+    ctl->fallback_rounds += 1;
+    ctl->committed = 0;
+  }
+}
+
+__global__ void k_end(Ctl* ctl) {
+  if (ctl->done) return;
+  if (ctl->fallback) ctl->O += (int64_t)ctl->k * ctl->dS2 - 2 * ctl->dN2;
+  ctl->moves += ctl->committed;
+  if (ctl->trace) {
+    int64_t* r = ctl->trace + (int64_t)(ctl->passes - 1) * 4;
+    r[0] = ctl->nprop;
+    r[1] = ctl->committed;
+    r[2] = ctl->fallback;
+    r[3] = ctl->O;
+  }
+  ctl->nprop = 0;
+  ctl->committed = 0;
+  ctl->fallback = 0;
+  ctl->dS2 = 0;
+  ctl->dN2 = 0;
+  if (ctl->passes >= ctl->max_rounds) ctl->done = 1;
+}
+
+__global__ void k_ctl_init(Ctl* ctl, const int64_t* acc, int32_t k, int32_t max_rounds,
+                           int64_t* trace) {
+  Ctl c = {};
+  c.k = k;
+  c.max_rounds = max_rounds;
+  c.trace = trace;
+  c.O = (int64_t)k * acc[0] + acc[1] - 2 * acc[2];
+  *ctl = c;
+}
+
+template <int G>
+void launch_score(const PassArgs& a, int grid, hipStream_t st) {
+  k_score<G><<<grid, kBlock, 0, st>>>(a);
+}
+
+}  // namespace
+
+int score_lanes_auto(int32_t k) {
+  if (k <= 8) return 8;
+  if (k <= 24) return 16;
+  if (k <= 64) return 16;
+  return 32;
+}
+
+bool score_lanes_ok(int lanes) {
+  return lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32 || lanes == 64;
+}
+
+void launch_ctl_init(Ctl* ctl, const int64_t* acc, int32_t k, int32_t max_rounds,
+                     int64_t* trace, hipStream_t st) {
+  k_ctl_init<<<1, 1, 0, st>>>(ctl, acc, k, max_rounds, trace);
+}
+
+void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, hipStream_t st) {
+  switch (lanes) {
+    case 4: launch_score<4>(a, grid_score, st); break;
+    case 8: launch_score<8>(a, grid_score, st); break;
+    case 16: launch_score<16>(a, grid_score, st); break;
+    case 32: launch_score<32>(a, grid_score, st); break;
+    default: launch_score<64>(a, grid_score, st); break;
+  }
+  k_begin<<<1, 1, 0, st>>>(a.ctl);
+  k_apply<kApplyAll><<<grid_apply, kBlock, 0, st>>>(a);
+  k_decide<<<1, 1, 0, st>>>(a.ctl);
+  k_apply<kCommitOrElect><<<grid_apply, kBlock, 0, st>>>(a);
+  k_apply<kFallbackCommit><<<grid_apply, kBlock, 0, st>>>(a);
+  k_apply<kFallbackFinish><<<grid_apply, kBlock, 0, st>>>(a);
+  k_end<<<1, 1, 0, st>>>(a.ctl);
+}
+
+}  // namespace mcc

@@ -1,0 +1,478 @@
+// Setup kernels of libmcc: label compaction and transpose, consensus-cluster
+// compaction, contingency-table build, objective reduction, CSR validation
+// and presentation relabelling.
+//
+// The contingency counts N_i(x, l) (members of consensus cluster x put in
+// cluster l by input partition i) and cluster sizes s_x are what the
+// closed-form gain of a move needs; the paper instead sums over cluster
+// members (Methods, "Computation and memory complexity"), which costs
+// O(|cluster| k) per candidate where these tables cost O(k).
+#include "impl.h"
+
+namespace mcc {
+
+namespace {
+
+inline int grid_for(int64_t items, int per_block, int cap = 65535) {
+  int64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+__device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ inline int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
+
+// exclusive scan of one value per thread over a kBlock-thread workgroup
+__device__ int32_t block_exclusive_scan(int32_t x, int32_t* total) {
+  __shared__ int32_t wsum[kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t v = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
+  }
+  if (lane == 63) wsum[w] = v;
+  __syncthreads();
+  int32_t off = 0, tot = 0;
+#pragma unroll
+  for (int j = 0; j < kBlock / 64; ++j) {
+    if (j < w) off += wsum[j];
+    tot += wsum[j];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + v - x;
+}
+
+template <typename T>
+__device__ T block_sum(T x) {
+  __shared__ T part[kBlock / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = x;
+  __syncthreads();
+  T t = 0;
+  if (threadIdx.x == 0)
+    for (int j = 0; j < kBlock / 64; ++j) t += part[j];
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+// ---- scan ------------------------------------------------------------------
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const int32_t* __restrict__ in,
+                                                        int64_t len, int32_t* __restrict__ tmp) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int32_t s = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    int64_t idx = base + (int64_t)j * kBlock + threadIdx.x;
+    if (idx < len) s += in[idx];
+  }
+  int32_t t = block_sum<int32_t>(s);
+  if (threadIdx.x == 0) tmp[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_top(int32_t* __restrict__ tmp, int64_t nb) {
+  int32_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+    int64_t idx = b0 + threadIdx.x;
+    int32_t x = idx < nb ? tmp[idx] : 0;
+    int32_t tot;
+    int32_t e = block_exclusive_scan(x, &tot);
+    if (idx < nb) tmp[idx] = carry + e;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) tmp[nb] = carry;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t* __restrict__ in, int64_t len,
+                                                      const int32_t* __restrict__ tmp,
+                                                      int32_t* __restrict__ out) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int32_t vals[kScanItems];
+  int32_t s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    int64_t idx = base + j;
+    vals[j] = idx < len ? in[idx] : 0;
+    s += vals[j];
+  }
+  int32_t tot;
+  int32_t run = tmp[blockIdx.x] + block_exclusive_scan(s, &tot);
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    int64_t idx = base + j;
+    if (idx < len) out[idx] = run;
+    run += vals[j];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[len] = tmp[gridDim.x];
+}
+
+// ---- labels ----------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_label_max(const int32_t* const* __restrict__ labels,
+                                                      int64_t n, int32_t* __restrict__ maxlab,
+                                                      int32_t* __restrict__ err) {
+  const int32_t* p = labels[blockIdx.y];
+  int32_t m = -1, bad = 0;
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    int32_t x = p[v];
+    bad |= x < 0;
+    m = max(m, x);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    m = max(m, __shfl_xor(m, o, 64));
+    bad |= __shfl_xor(bad, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&maxlab[blockIdx.y], m);
+    if (bad) atomicOr(err, kErrNegLabel);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_label_mark(const int32_t* const* __restrict__ labels,
+                                                       int64_t n, const int64_t* __restrict__ loff,
+                                                       int32_t* __restrict__ flags) {
+  const int32_t* p = labels[blockIdx.y];
+  int32_t* f = flags + loff[blockIdx.y];
+  for (int64_t v = gtid(); v < n; v += gstride()) f[p[v]] = 1;
+}
+
+__global__ void k_label_counts(const int32_t* __restrict__ scan, const int64_t* __restrict__ loff,
+                               int32_t k, int32_t* __restrict__ Lc) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) Lc[i] = scan[loff[i + 1]] - scan[loff[i]];
+}
+
+// Dense labels, transposed to vertex-major rows: Lvm[v * k + i] = id of
+// P_i(v).  A workgroup moves a tile of tv vertices x k partitions through
+// LDS so that both the partition-major reads and the row writes coalesce.
+__global__ __launch_bounds__(kBlock) void k_label_transpose(
+    const int32_t* const* __restrict__ labels, int32_t k, int64_t n,
+    const int64_t* __restrict__ loff, const int32_t* __restrict__ scan, int tv,
+    int32_t* __restrict__ Lvm) {
+  extern __shared__ int32_t tile[];  // [k][tv + 1]
+  const int64_t v0 = (int64_t)blockIdx.x * tv;
+  const int rows = min((int64_t)tv, n - v0);
+  for (int f = threadIdx.x; f < tv * k; f += kBlock) {
+    int vv = f % tv, i = f / tv;
+    if (vv < rows) {
+      int64_t off = loff[i];
+      tile[i * (tv + 1) + vv] = scan[off + labels[i][v0 + vv]] - scan[off];
+    }
+  }
+  __syncthreads();
+  int32_t* dst = Lvm + v0 * k;
+  for (int f = threadIdx.x; f < rows * k; f += kBlock) {
+    int vv = f / k, i = f % k;
+    dst[f] = tile[i * (tv + 1) + vv];
+  }
+}
+
+// ---- consensus clusters ----------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_cluster_mark(const int32_t* __restrict__ init, int64_t n,
+                                                         int32_t* __restrict__ flags,
+                                                         int32_t* __restrict__ err) {
+  int bad = 0;
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    int32_t x = init[v];
+    if (x < 0 || x >= n) bad = 1;
+    else flags[x] = 1;
+  }
+  if (bad) atomicOr(err, kErrInitRange);
+}
+
+__global__ __launch_bounds__(kBlock) void k_cluster_assign(const int32_t* __restrict__ init,
+                                                           int64_t n,
+                                                           const int32_t* __restrict__ cmap,
+                                                           int32_t* __restrict__ C,
+                                                           int32_t* __restrict__ rawid) {
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    C[v] = cmap[init[v]];
+    if (cmap[v + 1] > cmap[v]) rawid[cmap[v]] = (int32_t)v;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_iota(int32_t* __restrict__ a, int64_t n) {
+  for (int64_t v = gtid(); v < n; v += gstride()) a[v] = (int32_t)v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t x) {
+  for (int64_t v = gtid(); v < n; v += gstride()) a[v] = x;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u64(uint64_t* __restrict__ a, int64_t n,
+                                                     uint64_t x) {
+  for (int64_t v = gtid(); v < n; v += gstride()) a[v] = x;
+}
+
+// ---- contingency tables ------------------------------------------------------
+constexpr int kLdsHist = 16384;  // int32 entries privatised in LDS (64 KiB)
+
+// Workgroup (b, i) counts the pairs (C(v), P_i(v)) of its vertex range for
+// partition i.  When partition i's table fits kLdsHist entries the counts
+// are gathered in LDS and flushed once; otherwise they go straight to the
+// global table.
+__global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
+                                                  const int32_t* const* __restrict__ labels,
+                                                  const int64_t* __restrict__ loff,
+                                                  const int32_t* __restrict__ scan, int64_t n,
+                                                  int32_t K0, Tables t) {
+  __shared__ int32_t h[kLdsHist];
+  const int i = blockIdx.y;
+  const int32_t Li = t.L[i];
+  int32_t* Ni = t.N + t.toff[i];
+  const int64_t entries = (int64_t)K0 * Li;
+  const bool lds = entries <= kLdsHist;
+  if (lds) {
+    for (int j = threadIdx.x; j < entries; j += kBlock) h[j] = 0;
+    __syncthreads();
+  }
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t v0 = (int64_t)blockIdx.x * per;
+  const int64_t v1 = min(n, v0 + per);
+  // partition-major input labels (coalesced) mapped to dense ids
+  const int32_t* p = labels[i];
+  const int32_t* map = scan + loff[i];
+  const int32_t base = map[0];
+  for (int64_t v = v0 + threadIdx.x; v < v1; v += kBlock) {
+    int64_t idx = (int64_t)C[v] * Li + (map[p[v]] - base);
+    if (lds) atomicAdd(&h[idx], 1);
+    else atomicAdd(&Ni[idx], 1);
+  }
+  if (lds) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < entries; j += kBlock)
+      if (h[j]) atomicAdd(&Ni[j], h[j]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sizes(const int32_t* __restrict__ C, int64_t n,
+                                                  int32_t K0, int32_t* __restrict__ s) {
+  __shared__ int32_t h[kLdsHist];
+  const bool lds = K0 <= kLdsHist;
+  if (lds) {
+    for (int j = threadIdx.x; j < K0; j += kBlock) h[j] = 0;
+    __syncthreads();
+  }
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    if (lds) atomicAdd(&h[C[v]], 1);
+    else atomicAdd(&s[C[v]], 1);
+  }
+  if (lds) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < K0; j += kBlock)
+      if (h[j]) atomicAdd(&s[j], h[j]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sumsq(const int32_t* __restrict__ a, int64_t len,
+                                                  int64_t* __restrict__ acc) {
+  int64_t s = 0;
+  for (int64_t j = gtid(); j < len; j += gstride()) {
+    int64_t x = a[j];
+    s += x * x;
+  }
+  s = block_sum<int64_t>(s);
+  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)acc, (unsigned long long)s);
+}
+
+// sum over labels l of partition i of |P_i l|^2, with |P_i l| = sum_x N_i(x, l)
+__global__ __launch_bounds__(kBlock) void k_hist_sumsq(Tables t, int32_t K0,
+                                                       int64_t* __restrict__ acc) {
+  const int i = blockIdx.y;
+  const int32_t Li = t.L[i];
+  const int32_t* Ni = t.N + t.toff[i];
+  int64_t s = 0;
+  for (int64_t l = gtid(); l < Li; l += gstride()) {
+    int64_t h = 0;
+    for (int32_t x = 0; x < K0; ++x) h += Ni[(int64_t)x * Li + l];
+    s += h * h;
+  }
+  s = block_sum<int64_t>(s);
+  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)acc, (unsigned long long)s);
+}
+
+// ---- validation, output ----------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_validate_csr(const int64_t* __restrict__ row_ptr,
+                                                         const int32_t* __restrict__ col,
+                                                         int64_t n, int64_t nnz,
+                                                         int32_t* __restrict__ err) {
+  int bad = 0;
+  if (gtid() == 0 && (row_ptr[0] != 0 || row_ptr[n] != nnz)) bad = 1;
+  for (int64_t v = gtid(); v < n; v += gstride())
+    if (row_ptr[v + 1] < row_ptr[v]) bad = 1;
+  for (int64_t j = gtid(); j < nnz; j += gstride())
+    if (col[j] < 0 || col[j] >= n) bad = 1;
+  if (bad) atomicOr(err, kErrGraph);
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish(const int32_t* __restrict__ C,
+                                                   const int32_t* __restrict__ rawid, int64_t n,
+                                                   int32_t* __restrict__ out) {
+  for (int64_t v = gtid(); v < n; v += gstride()) out[v] = rawid[C[v]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_count_nonzero(const int32_t* __restrict__ a, int64_t n,
+                                                          int32_t* __restrict__ count) {
+  int32_t c = 0;
+  for (int64_t j = gtid(); j < n; j += gstride()) c += a[j] != 0;
+  c = block_sum<int32_t>(c);
+  if (threadIdx.x == 0 && c) atomicAdd(count, c);
+}
+
+__global__ __launch_bounds__(kBlock) void k_first_occurrence(const int32_t* __restrict__ in,
+                                                             int64_t n, int32_t* __restrict__ first) {
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    int32_t x = in[v];
+    if (__hip_atomic_load(&first[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > v)
+      atomicMin(&first[x], (int32_t)v);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_first_flags(const int32_t* __restrict__ in, int64_t n,
+                                                        const int32_t* __restrict__ first,
+                                                        int32_t* __restrict__ flags) {
+  for (int64_t v = gtid(); v < n; v += gstride()) flags[v] = first[in[v]] == v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_canonical_write(const int32_t* __restrict__ in,
+                                                            int64_t n,
+                                                            const int32_t* __restrict__ first,
+                                                            const int32_t* __restrict__ rank,
+                                                            int32_t* __restrict__ out) {
+  for (int64_t v = gtid(); v < n; v += gstride()) out[v] = rank[first[in[v]]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_dense_map(const int32_t* __restrict__ in, int64_t n,
+                                                      const int32_t* __restrict__ scan,
+                                                      int32_t* __restrict__ out) {
+  const int32_t base = scan[0];
+  for (int64_t v = gtid(); v < n; v += gstride()) out[v] = scan[in[v]] - base;
+}
+
+}  // namespace
+
+// ---- launchers ---------------------------------------------------------------
+int64_t scan_tmp_elems(int64_t len) { return (len + kScanTile - 1) / kScanTile + 2; }
+
+void launch_scan(const int32_t* in, int32_t* out, int64_t len, int32_t* tmp, hipStream_t st) {
+  // out[j] = sum_{t < j} in[t] for j in [0, len]; out may alias in
+  int64_t nb = (len + kScanTile - 1) / kScanTile;
+  if (nb < 1) nb = 1;
+  k_scan_reduce<<<(unsigned)nb, kBlock, 0, st>>>(in, len, tmp);
+  k_scan_top<<<1, kBlock, 0, st>>>(tmp, nb);
+  k_scan_down<<<(unsigned)nb, kBlock, 0, st>>>(in, len, tmp, out);
+}
+
+void launch_label_max(const int32_t* const* dlabels, int32_t k, int64_t n, int32_t* maxlab,
+                      int32_t* err, hipStream_t st) {
+  dim3 g(grid_for(n, kBlock, 256), k);
+  k_label_max<<<g, kBlock, 0, st>>>(dlabels, n, maxlab, err);
+}
+
+void launch_label_mark(const int32_t* const* dlabels, int32_t k, int64_t n, const int64_t* loff,
+                       int32_t* flags, hipStream_t st) {
+  dim3 g(grid_for(n, kBlock, 256), k);
+  k_label_mark<<<g, kBlock, 0, st>>>(dlabels, n, loff, flags);
+}
+
+void launch_label_counts(const int32_t* scan, const int64_t* loff, int32_t k, int32_t* Lc,
+                         hipStream_t st) {
+  k_label_counts<<<grid_for(k, kBlock), kBlock, 0, st>>>(scan, loff, k, Lc);
+}
+
+void launch_label_transpose(const int32_t* const* dlabels, int32_t k, int64_t n,
+                            const int64_t* loff, const int32_t* scan, int32_t* Lvm,
+                            hipStream_t st) {
+  int tv = 64;
+  while (tv > 1 && (int64_t)(tv + 1) * k * 4 > 48 * 1024) tv >>= 1;
+  size_t lds = (size_t)(tv + 1) * k * sizeof(int32_t);
+  int64_t nb = (n + tv - 1) / tv;
+  k_label_transpose<<<(unsigned)nb, kBlock, lds, st>>>(dlabels, k, n, loff, scan, tv, Lvm);
+}
+
+void launch_cluster_mark(const int32_t* init, int64_t n, int32_t* flags, int32_t* err,
+                         hipStream_t st) {
+  k_cluster_mark<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(init, n, flags, err);
+}
+
+void launch_cluster_assign(const int32_t* init, int64_t n, const int32_t* cmap, int32_t* C,
+                           int32_t* rawid, hipStream_t st) {
+  k_cluster_assign<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(init, n, cmap, C, rawid);
+}
+
+void launch_iota(int32_t* a, int64_t n, hipStream_t st) {
+  k_iota<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(a, n);
+}
+
+void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st) {
+  if (n > 0) k_fill_i32<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(a, n, v);
+}
+
+void launch_fill_u64(uint64_t* a, int64_t n, uint64_t v, hipStream_t st) {
+  if (n > 0) k_fill_u64<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(a, n, v);
+}
+
+void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t* loff,
+                  const int32_t* scan, int64_t n, int32_t k, int32_t K0, Tables t, int32_t* s,
+                  hipStream_t st) {
+  // enough workgroups per partition to fill the chip, few enough that the
+  // LDS flush stays small next to the counting
+  int64_t per_part = (n + 4095) / 4096;
+  if (per_part > 64) per_part = 64;
+  if (per_part < 1) per_part = 1;
+  dim3 g((unsigned)per_part, k);
+  k_build<<<g, kBlock, 0, st>>>(C, dlabels, loff, scan, n, K0, t);
+  k_sizes<<<grid_for(n, kBlock * 16, 512), kBlock, 0, st>>>(C, n, K0, s);
+}
+
+void launch_objective0(const Tables& t, int32_t k, int32_t K0, const int32_t* s,
+                       int64_t total_entries, int64_t* acc, hipStream_t st) {
+  // acc[0] += sum_x s_x^2; acc[1] += sum_i sum_l |P_i l|^2;
+  // acc[2] += sum_i sum_(x,l) N_i(x,l)^2 over all `total_entries` table cells
+  k_sumsq<<<grid_for(K0, kBlock, 1024), kBlock, 0, st>>>(s, K0, acc);
+  dim3 g(64, k);
+  k_hist_sumsq<<<g, kBlock, 0, st>>>(t, K0, acc + 1);
+  k_sumsq<<<grid_for(total_entries, kBlock, 2048), kBlock, 0, st>>>(t.N, total_entries, acc + 2);
+}
+
+void launch_validate_csr(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
+                         int32_t* err, hipStream_t st) {
+  k_validate_csr<<<grid_for(nnz > n ? nnz : n, kBlock, 2048), kBlock, 0, st>>>(row_ptr, col, n,
+                                                                               nnz, err);
+}
+
+void launch_finish(const int32_t* C, const int32_t* rawid, int64_t n, int32_t* out,
+                   hipStream_t st) {
+  k_finish<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(C, rawid, n, out);
+}
+
+void launch_count_nonzero(const int32_t* a, int64_t n, int32_t* count, hipStream_t st) {
+  k_count_nonzero<<<grid_for(n, kBlock, 1024), kBlock, 0, st>>>(a, n, count);
+}
+
+void launch_first_occurrence(const int32_t* in, int64_t n, int32_t* first, hipStream_t st) {
+  k_first_occurrence<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(in, n, first);
+}
+
+void launch_first_flags(const int32_t* in, int64_t n, const int32_t* first, int32_t* flags,
+                        hipStream_t st) {
+  k_first_flags<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(in, n, first, flags);
+}
+
+void launch_canonical_write(const int32_t* in, int64_t n, const int32_t* first,
+                            const int32_t* rank, int32_t* out, hipStream_t st) {
+  k_canonical_write<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(in, n, first, rank, out);
+}
+
+void launch_dense_map(const int32_t* in, int64_t n, const int32_t* scan, int32_t* out,
+                      hipStream_t st) {
+  k_dense_map<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(in, n, scan, out);
+}
+
+}  // namespace mcc

@@ -126,7 +126,7 @@ def lfr(n=100_000, k=32, w=1, mean_deg=20.0, max_deg=200, mu=0.4,
     return _finish("lfr", row_ptr, col, labels, truth, dict(workload=w, **info))
 
 
-def gmm_knn(n=2_000_000, k=50, w=2, dim=30, ncomp=50, zipf_a=1.2, sigma_m=0.5, nn=15,
+def gmm_knn(n=2_000_000, k=50, w=2, dim=30, ncomp=50, zipf_a=1.2, sigma_m=0.8, nn=15,
             device="cpu", chunk=0):
     rng = graph_rng(w)
     pts, truth = G.gmm_points(n, dim, ncomp, zipf_a, sigma_m, rng)

@@ -1,0 +1,242 @@
+"""GPU parity: libmcc against the CPU oracle, bit for bit, through the C-ABI.
+
+Every comparison is exact (integer work): output cluster ids, objective,
+passes, moves, fallback rounds, candidate evaluations and the per-pass
+trace.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth import graph as G
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+KEYS = ("passes", "converged", "fallback_rounds", "clusters", "moves", "candidate_evals",
+        "objective_init", "objective")
+
+
+@pytest.fixture(scope="module")
+def mcc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2408_11331_amd as m
+    m.lib()  # fails loudly when the library is missing
+    oracle.build(force=False)
+    return m
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def run_gpu(mcc, inst, init="inst", **kw):
+    import torch
+    ini = inst.init if isinstance(init, str) else init
+    out, st, tr = mcc.consensus(dev(inst.row_ptr), dev(inst.col), dev(inst.labels),
+                                None if ini is None else dev(ini), trace=True, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), st, np.array(tr, dtype=np.int64).reshape(-1, 4)
+
+
+def run_oracle(inst, init="inst", **kw):
+    ini = inst.init if isinstance(init, str) else init
+    return oracle.consensus(inst.row_ptr, inst.col, inst.labels, ini, trace=True, **kw)
+
+
+def assert_same(g, o):
+    gout, gst, gtr = g
+    oout, ost, otr = o
+    assert np.array_equal(gout, oout)
+    for key in KEYS:
+        assert gst[key] == ost[key], (key, gst[key], ost[key])
+    assert np.array_equal(gtr, otr)
+
+
+def complete(n):
+    u, v = np.triu_indices(n, 1)
+    return G.csr_from_edges(n, u, v)
+
+
+# ---------------------------------------------------------------- worked ----
+def test_golden_s5(mcc):
+    announce("golden s5")
+    g = json.load(open(os.path.join(GOLDEN, "s5_k6_trace.json")))
+    rp, col = complete(g["n"])
+    inst = synth.Instance("s5", rp, col, np.array(g["labels"], np.int32),
+                          np.array(g["init"], np.int32), np.zeros(6, np.int32), {})
+    out, st, tr = run_gpu(mcc, inst)
+    e = g["expected"]
+    assert out.tolist() == e["out"]
+    for key in ("passes", "moves", "fallback_rounds", "converged", "objective_init",
+                "objective", "candidate_evals"):
+        assert st[key] == e[key], key
+    assert tr.tolist() == e["trace"]
+
+
+# ------------------------------------------------------- small / ragged -----
+CASES = []
+for seed in range(24):
+    r = np.random.Generator(np.random.PCG64(seed))
+    n = int(r.choice([1, 2, 3, 17, 63, 64, 65, 200, 777, 2000]))
+    k = int(r.choice([1, 2, 5, 16, 33, 64, 65, 70]))
+    init = ["p0", "singleton", "random"][seed % 3]
+    CASES.append((seed, n, k, init))
+
+
+@pytest.mark.parametrize("seed,n,k,init", CASES)
+def test_random_instances(mcc, seed, n, k, init):
+    announce(f"random seed={seed} n={n} k={k} init={init}")
+    inst = synth.random_instance(n, k, avg_deg=[0.0, 3.0, 8.0, 40.0][seed % 4],
+                                 n_labels=[1, 3, 7, 50][(seed // 4) % 4], seed=seed, init=init,
+                                 self_loops=seed % 5, dup_arcs=2 * (seed % 3))
+    ini = None if init == "singleton" else inst.init
+    o = run_oracle(inst, ini)
+    for lanes in (0, [4, 8, 16, 32, 64][seed % 5]):
+        assert_same(run_gpu(mcc, inst, ini, lanes=lanes), o)
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
+def test_high_degree_and_many_candidates(mcc, lanes):
+    # hubs beyond the register budget and candidate sets larger than a group
+    announce(f"hubs lanes={lanes}")
+    r = np.random.Generator(np.random.PCG64(77))
+    n, k = 3000, 9
+    u = np.concatenate([np.zeros(2500, np.int64), r.integers(0, n, 6000)])
+    v = np.concatenate([np.arange(1, 2501), r.integers(0, n, 6000)])
+    rp, col = G.csr_from_edges(n, u, v)
+    labels = r.integers(0, 40, size=(k, n)).astype(np.int32)
+    init = r.integers(0, 600, size=n).astype(np.int32)
+    inst = synth.Instance("hub", rp, col, labels, init, init, {})
+    assert_same(run_gpu(mcc, inst, lanes=lanes), run_oracle(inst))
+
+
+def test_literal_self_term_ablation(mcc):
+    announce("literal")
+    inst = synth.sbm_small()
+    assert_same(run_gpu(mcc, inst, flags=mcc.MCC_F_LITERAL), run_oracle(inst, literal=True))
+
+
+@pytest.mark.parametrize("max_rounds", [1, 2, 3])
+def test_max_rounds(mcc, max_rounds):
+    announce(f"max_rounds={max_rounds}")
+    inst = synth.random_instance(500, 6, 6.0, 5, seed=3, init="singleton")
+    assert_same(run_gpu(mcc, inst, None, max_rounds=max_rounds),
+                run_oracle(inst, None, max_rounds=max_rounds))
+
+
+def test_fallback_swap_instance(mcc):
+    # many copies of the K6 swap: forces fallback rounds at scale
+    announce("swap")
+    blocks = 400
+    us, vs = [], []
+    for b in range(blocks):
+        u, v = np.triu_indices(6, 1)
+        us.append(u + 6 * b)
+        vs.append(v + 6 * b)
+    n = 6 * blocks
+    rp, col = G.csr_from_edges(n, np.concatenate(us), np.concatenate(vs))
+    labels = np.stack([np.repeat(np.arange(blocks), 6)] * 3).astype(np.int32)
+    init = (np.repeat(np.arange(blocks) * 2, 6) + np.tile([0, 0, 0, 1, 1, 1], blocks)).astype(np.int32)
+    inst = synth.Instance("swap", rp, col, labels, init, init, {})
+    g = run_gpu(mcc, inst)
+    assert g[1]["fallback_rounds"] >= 1
+    assert_same(g, run_oracle(inst))
+
+
+# -------------------------------------------------------------- workloads ---
+def test_sbm_small_full(mcc):
+    announce("sbm_small n=1000 k=10")
+    inst = synth.sbm_small()
+    assert_same(run_gpu(mcc, inst), run_oracle(inst))
+    # singleton initialisation (the paper's) on the same graph
+    assert_same(run_gpu(mcc, inst, None), run_oracle(inst, None))
+
+
+def test_gmm_knn_reduced(mcc):
+    announce("gmm_knn n=20000 k=50")
+    inst = synth.gmm_knn(n=20000)
+    assert_same(run_gpu(mcc, inst), run_oracle(inst))
+
+
+def test_lfr_full(mcc):
+    announce("lfr n=100000 k=32")
+    inst = synth.lfr()
+    assert_same(run_gpu(mcc, inst), run_oracle(inst))
+
+
+# ------------------------------------------------------ other entry points --
+def test_mirkin_objective_canonicalize(mcc):
+    announce("mirkin/objective/canonicalize")
+    r = np.random.Generator(np.random.PCG64(5))
+    for n in (1, 5, 1000, 70001):
+        a = r.integers(0, max(1, n // 7), size=n).astype(np.int32)
+        b = (r.integers(0, 13, size=n) * 1_000_003 % (2 ** 31 - 1)).astype(np.int32)
+        assert mcc.mirkin(dev(a), dev(b)) == oracle.mirkin(a, b)
+        labels = r.integers(0, 9, size=(5, n)).astype(np.int32)
+        c = r.integers(0, n, size=n).astype(np.int32)
+        assert mcc.objective(dev(c), dev(labels)) == oracle.objective(c, labels)
+        out, cl = mcc.canonicalize(dev(c))
+        eout, ecl = oracle.canonicalize(c)
+        assert cl == ecl and np.array_equal(out.cpu().numpy(), eout)
+
+
+def test_determinism_and_resume(mcc):
+    announce("determinism/resume")
+    inst = synth.gmm_knn(n=5000)
+    a = run_gpu(mcc, inst)
+    b = run_gpu(mcc, inst)
+    assert np.array_equal(a[0], b[0]) and a[1]["objective"] == b[1]["objective"]
+    out, st, _ = run_gpu(mcc, inst, a[0])
+    assert np.array_equal(out, a[0]) and st["passes"] == 1 and st["moves"] == 0
+
+
+def test_error_paths(mcc):
+    announce("errors")
+    import torch
+    inst = synth.random_instance(50, 3, 4.0, 4, seed=9)
+    rp, col, lab, ini = dev(inst.row_ptr), dev(inst.col), dev(inst.labels), dev(inst.init)
+    bad = lab.clone()
+    bad[1, 7] = -3
+    with pytest.raises(mcc.MccError) as e:
+        mcc.consensus(rp, col, bad, ini)
+    assert e.value.code == mcc.MCC_EINVAL
+    with pytest.raises(mcc.MccError) as e:
+        mcc.consensus(rp, col, lab, torch.full_like(ini, 50))
+    assert e.value.code == mcc.MCC_EINVAL
+    badcol = col.clone()
+    badcol[0] = 50
+    with pytest.raises(mcc.MccError) as e:
+        mcc.consensus(rp, badcol, lab, ini, flags=mcc.MCC_F_VALIDATE)
+    assert e.value.code == mcc.MCC_EGRAPH
+    badrp = rp.clone()
+    badrp[3] = badrp[4] + 1
+    with pytest.raises(mcc.MccError) as e:
+        mcc.consensus(badrp, col, lab, ini, flags=mcc.MCC_F_VALIDATE)
+    assert e.value.code == mcc.MCC_EGRAPH
+    # a host pointer where a device pointer is required
+    import ctypes
+    host = torch.zeros(50, dtype=torch.int32)
+    g = mcc.Csr(50, col.numel(), rp.data_ptr(), col.data_ptr())
+    arr = (ctypes.c_void_p * 3)(*[lab[i].data_ptr() for i in range(3)])
+    rc = mcc.lib().mcc_consensus(ctypes.byref(g), arr, 3, None, host.data_ptr(), None)
+    assert rc == mcc.MCC_EINVAL
+    # empty input
+    out, st = mcc.consensus(dev(np.zeros(1, np.int64)), dev(np.zeros(0, np.int32)),
+                            dev(np.zeros((2, 0), np.int32)))
+    assert out.numel() == 0 and st["passes"] == 1 and st["converged"] == 1
