@@ -50,6 +50,8 @@ extern "C" {
                                whose sum over u includes u = v and so adds k to
                                every gain (an ablation; default is the exact
                                gain) */
+#define MCC_F_PROFILE 0x8u  /* time every scoring kernel with HIP events on the
+                               call's stream (stats->ms_score) */
 
 /* CSR graph: row_ptr[n + 1] (int64, row_ptr[0] = 0, non-decreasing,
  * row_ptr[n] = nnz) and col[nnz] (int32 vertex ids in [0, n)).  Arcs are
@@ -90,6 +92,11 @@ typedef struct {
   int64_t objective;       /* sum_i Mirkin(out, P_i) */
   float ms_total;          /* wall time of the call on the stream */
   float ms_passes;         /* time spent in the pass loop */
+  int64_t boundary;        /* sum over passes of the vertices that had at
+                              least one candidate (their label rows are read) */
+  float ms_score;          /* with MCC_F_PROFILE: summed duration of the
+                              scoring kernels of the executed passes */
+  int32_t lanes_used;      /* lanes per vertex the scoring kernel ran with */
 } mcc_stats;
 
 /*

@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmcc.so")
 
 MCC_OK, MCC_EINVAL, MCC_EGRAPH, MCC_ENOMEM, MCC_EDEVICE, MCC_ENOTSUP = 0, -1, -2, -3, -4, -5
-MCC_F_VALIDATE, MCC_F_TRACE, MCC_F_LITERAL = 0x1, 0x2, 0x4
+MCC_F_VALIDATE, MCC_F_TRACE, MCC_F_LITERAL, MCC_F_PROFILE = 0x1, 0x2, 0x4, 0x8
 
 # every function include/mcc.h declares
 EXPORTS = ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize", "mcc_strerror")
@@ -35,10 +35,13 @@ class Stats(ctypes.Structure):
         ("moves", ctypes.c_int64), ("candidate_evals", ctypes.c_int64),
         ("objective_init", ctypes.c_int64), ("objective", ctypes.c_int64),
         ("ms_total", ctypes.c_float), ("ms_passes", ctypes.c_float),
+        ("boundary", ctypes.c_int64), ("ms_score", ctypes.c_float),
+        ("lanes_used", ctypes.c_int32),
     ]
 
     OUT = ("passes", "converged", "fallback_rounds", "clusters", "moves", "candidate_evals",
-           "objective_init", "objective", "ms_total", "ms_passes")
+           "objective_init", "objective", "ms_total", "ms_passes", "boundary", "ms_score",
+           "lanes_used")
 
     def as_dict(self):
         return {f: getattr(self, f) for f in self.OUT}

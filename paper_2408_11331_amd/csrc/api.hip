@@ -129,8 +129,10 @@ struct Compacted {
   const int32_t* const* dlabels = nullptr;
   int64_t* loff = nullptr;  // device, k + 1
   int32_t* scan = nullptr;  // device, loff[k] + 1
-  int32_t* L = nullptr;     // device, k
+  int32_t* fmap = nullptr;  // device, loff[k] + 1: id of raw label x at loff[i] + x
+  int32_t* L = nullptr;     // device, k: dense label count per partition
   std::vector<int32_t> Lh;  // host copy
+  int64_t max_span = 0;     // largest maxlab + 1
 };
 
 // Everything the passes need, built from the partitions and an initial
@@ -144,11 +146,36 @@ struct Solve {
   int32_t* rawid = nullptr;
   int32_t* Lvm = nullptr;
   int32_t* s = nullptr;
-  int64_t* toff = nullptr;
-  int32_t* N = nullptr;
-  int64_t total = 0;
+  Tables t{};
+  int32_t maxL = 0;        // largest label id bound of the final tables
+  int64_t total = 0;       // table cells
   int64_t* acc = nullptr;  // sum s^2, sum |P_il|^2, sum N^2
 };
+
+// Largest cluster count for which labels are aligned to clusters.
+constexpr int32_t kAlignMaxClusters = 1 << 16;
+
+// Blocked tables for the current label ids: allocation, zero fill, build.
+Tables blocked_tables(Arena& ar, const Solve& S, const int32_t* Ldev,
+                      const std::vector<int32_t>& Lh, hipStream_t st, int64_t* total) {
+  const int32_t k = S.k;
+  std::vector<int64_t> toff(k + 1, 0);
+  for (int i = 0; i < k; ++i) toff[i + 1] = toff[i] + (int64_t)S.K0 * Lh[i];
+  if (toff[k] > kMaxTableEntries) throw Status{MCC_ENOTSUP};
+  int64_t* dtoff = ar.get<int64_t>(k + 1);
+  h2d(dtoff, ar.host(toff), k + 1, st);
+  int32_t* N = ar.get<int32_t>(toff[k]);
+  launch_fill_i32(N, toff[k], 0, st);
+  *total = toff[k];
+  Tables t;
+  t.N = N;
+  t.toff = dtoff;
+  t.L = Ldev;
+  t.Lmax = 0;
+  t.k = k;
+  t.interleaved = 0;
+  return t;
+}
 
 // Stage 1: label ranges, optional init-range and CSR checks.
 void compact_labels(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
@@ -181,6 +208,10 @@ void compact_labels_finish(Arena& ar, int64_t n, int32_t k, const std::vector<in
   launch_scan(flags, out->scan, loff[k], tmp, st);
   out->L = ar.get<int32_t>(k);
   launch_label_counts(out->scan, out->loff, k, out->L, st);
+  out->max_span = 1;
+  for (int i = 0; i < k; ++i) out->max_span = std::max<int64_t>(out->max_span, loff[i + 1] - loff[i]);
+  out->fmap = ar.get<int32_t>(loff[k] + 1);
+  launch_label_ids(out->scan, out->loff, k, out->max_span, out->fmap, st);
 }
 
 // The full setup: compaction of labels and clusters, tables, initial
@@ -222,13 +253,6 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
   sync(st);
   S->K0 = K0;
 
-  std::vector<int64_t> toff(k + 1, 0);
-  for (int i = 0; i < k; ++i) toff[i + 1] = toff[i] + (int64_t)K0 * S->lab.Lh[i];
-  S->total = toff[k];
-  if (S->total > kMaxTableEntries) throw Status{MCC_ENOTSUP};
-  S->toff = ar.get<int64_t>(k + 1);
-  h2d(S->toff, ar.host(toff), k + 1, st);
-
   S->C = ar.get<int32_t>(n);
   S->rawid = ar.get<int32_t>(K0);
   if (init) {
@@ -237,19 +261,70 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
     launch_iota(S->C, n, st);
     launch_iota(S->rawid, n, st);
   }
-  if (want_rows) {
-    S->Lvm = ar.get<int32_t>(n * k);
-    launch_label_transpose(S->lab.dlabels, k, n, S->lab.loff, S->lab.scan, S->Lvm, st);
-  }
-  S->N = ar.get<int32_t>(S->total);
-  launch_fill_i32(S->N, S->total, 0, st);
   S->s = ar.get<int32_t>(K0);
   launch_fill_i32(S->s, K0, 0, st);
-  Tables t{S->N, S->toff, S->lab.L};
-  launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.scan, n, k, K0, t, S->s, st);
+  launch_sizes(S->C, n, K0, S->s, st);
+
+  const std::vector<int32_t>& Lh = S->lab.Lh;
+  int32_t maxL = 1;
+  int64_t sumL = 0;
+  for (int i = 0; i < k; ++i) {
+    maxL = std::max(maxL, Lh[i]);
+    sumL += Lh[i];
+  }
+  // Blocked tables with dense label ids: the final tables when the labels
+  // are not aligned, the source of the alignment otherwise.
+  int64_t total = 0;
+  Tables bt = blocked_tables(ar, *S, S->lab.L, Lh, st, &total);
+  launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, bt, st);
+  S->t = bt;
+  S->maxL = maxL;
+  S->total = total;
+
+  if (want_rows && K0 <= kAlignMaxClusters) {
+    std::vector<int64_t> poff(k + 1, 0);
+    for (int i = 0; i < k; ++i) poff[i + 1] = poff[i] + Lh[i];
+    int64_t* dpoff = ar.get<int64_t>(k + 1);
+    h2d(dpoff, ar.host(poff), k + 1, st);
+    uint64_t* win = ar.get<uint64_t>((int64_t)k * K0);
+    int32_t* home = ar.get<int32_t>(sumL);
+    uint64_t* key = ar.get<uint64_t>(sumL);
+    int32_t* extra = ar.get<int32_t>(sumL + 1);
+    int32_t* rank = ar.get<int32_t>(sumL + 1);
+    int32_t* tmp = ar.get<int32_t>(scan_tmp_elems(sumL));
+    int32_t* amap = ar.get<int32_t>(sumL);
+    int32_t* L2 = ar.get<int32_t>(k);
+    launch_align(bt, k, K0, maxL, dpoff, sumL, win, home, key, extra, rank, tmp, amap, L2, st);
+    std::vector<int32_t> L2h(k, 0);
+    d2h(L2h.data(), L2, k, st);
+    sync(st);
+    int32_t Lmax = 1;
+    for (int i = 0; i < k; ++i) Lmax = std::max(Lmax, L2h[i]);
+    const int64_t cells = (int64_t)K0 * Lmax * k;
+    if (cells <= kMaxTableEntries && cells <= 2 * total + ((int64_t)1 << 20)) {
+      launch_fmap_update(S->lab.scan, S->lab.loff, dpoff, amap, k, S->lab.max_span,
+                         S->lab.fmap, st);
+      Tables it;
+      it.N = ar.get<int32_t>(cells);
+      launch_fill_i32(it.N, cells, 0, st);
+      it.toff = nullptr;
+      it.L = L2;
+      it.Lmax = Lmax;
+      it.k = k;
+      it.interleaved = 1;
+      launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, it, st);
+      S->t = it;
+      S->maxL = Lmax;
+      S->total = cells;
+    }
+  }
+  if (want_rows) {
+    S->Lvm = ar.get<int32_t>(n * k);
+    launch_label_transpose(S->lab.dlabels, k, n, S->lab.loff, S->lab.fmap, S->Lvm, st);
+  }
   S->acc = ar.get<int64_t>(3);
   launch_fill_u64(reinterpret_cast<uint64_t*>(S->acc), 3, 0ull, st);
-  launch_objective0(t, k, K0, S->s, S->total, S->acc, st);
+  launch_objective0(S->t, k, K0, S->maxL, S->s, S->total, S->acc, st);
 }
 
 int translate(const std::exception_ptr& ep) {
@@ -305,7 +380,9 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
   if (stats) {
     stats->passes = stats->converged = stats->fallback_rounds = stats->clusters = 0;
     stats->moves = stats->candidate_evals = stats->objective_init = stats->objective = 0;
-    stats->ms_total = stats->ms_passes = 0.f;
+    stats->ms_total = stats->ms_passes = stats->ms_score = 0.f;
+    stats->boundary = 0;
+    stats->lanes_used = 0;
   }
   if (n == 0) {
     if (stats) {
@@ -359,7 +436,7 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
     a.col = g->col;
     a.C = S.C;
     a.Lvm = S.Lvm;
-    a.t = Tables{S.N, S.toff, S.lab.L};
+    a.t = S.t;
     a.s = S.s;
     a.prop = prop;
     a.dprop = dprop;
@@ -372,13 +449,31 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
     const int grid_apply =
         (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, sms * 4));
 
+    const bool profile = (flags & MCC_F_PROFILE) != 0;
+    std::vector<hipEvent_t> pev;  // begin/end of every enqueued scoring kernel
+    struct EvList {
+      std::vector<hipEvent_t>* v;
+      ~EvList() {
+        for (hipEvent_t e : *v) (void)hipEventDestroy(e);
+      }
+    } pev_guard{&pev};
+
     HIPCK(hipEventRecord(e1, st));
     Ctl hc;
     memset(&hc, 0, sizeof hc);
     int enqueued = 0, chunk = 2;
     while (enqueued < max_rounds) {
       const int todo = std::min(chunk, max_rounds - enqueued);
-      for (int j = 0; j < todo; ++j) enqueue_pass(a, lanes, grid_score, grid_apply, st);
+      for (int j = 0; j < todo; ++j) {
+        hipEvent_t b = nullptr, e = nullptr;
+        if (profile) {
+          HIPCK(hipEventCreate(&b));
+          pev.push_back(b);
+          HIPCK(hipEventCreate(&e));
+          pev.push_back(e);
+        }
+        enqueue_pass(a, lanes, grid_score, grid_apply, st, b, e);
+      }
       enqueued += todo;
       d2h(&hc, ctl, 1, st);
       sync(st);
@@ -417,6 +512,16 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
       stats->ms_total = ms;
       HIPCK(hipEventElapsedTime(&ms, e1, e2));
       stats->ms_passes = ms;
+      stats->boundary = hc.boundary;
+      stats->lanes_used = lanes;
+      if (profile) {
+        float tot = 0.f;
+        for (int j = 0; j < hc.passes && 2 * j + 1 < (int)pev.size(); ++j) {
+          HIPCK(hipEventElapsedTime(&ms, pev[2 * j], pev[2 * j + 1]));
+          tot += ms;
+        }
+        stats->ms_score = tot;
+      }
     }
     return MCC_OK;
   } catch (...) {

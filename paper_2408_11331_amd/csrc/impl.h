@@ -30,6 +30,7 @@ struct Ctl {
   int64_t dN2;              // change of sum_i sum_(c,l) N_i(c,l)^2, same
   int64_t O;                // current objective sum_i Mirkin(C, P_i)
   int64_t moves;            // committed moves in all passes
+  int64_t boundary;         // vertices with a candidate, summed over passes
   int64_t* trace;           // device int64[max_rounds * 4] or null
 };
 
@@ -37,14 +38,27 @@ constexpr int32_t kErrNegLabel = 1;
 constexpr int32_t kErrInitRange = 2;
 constexpr int32_t kErrGraph = 4;
 
-// Dense contingency tables: for partition i, the count of vertices of
-// consensus cluster x (dense index) whose dense label in P_i is l sits at
-// N[toff[i] + x * L[i] + l].
+// Dense contingency tables N_i(x, l): the number of vertices of consensus
+// cluster x (dense index) whose label id in partition i is l.  Two layouts:
+//  - blocked:     N[toff[i] + x * L[i] + l], one block per partition;
+//  - interleaved: N[(x * Lmax + l) * k + i], the k partitions of one
+//    (cluster, label id) pair side by side.  With label ids aligned to the
+//    consensus cluster each label mostly overlaps (any injective relabelling
+//    leaves every count unchanged), the k probes of one vertex and cluster
+//    mostly fall into one cache line.
 struct Tables {
   int32_t* N;
-  const int64_t* toff;
-  const int32_t* L;
+  const int64_t* toff;  // blocked: start of partition i
+  const int32_t* L;     // ids of partition i lie in [0, L[i])
+  int32_t Lmax;         // interleaved: ids of every partition lie in [0, Lmax)
+  int32_t k;
+  int32_t interleaved;
 };
+
+__host__ __device__ inline int64_t cell(const Tables& t, int i, int32_t x, int32_t l) {
+  return t.interleaved ? ((int64_t)x * t.Lmax + l) * t.k + i
+                       : t.toff[i] + (int64_t)x * t.L[i] + l;
+}
 
 // ---- setup kernels (setup.hip) -------------------------------------------
 void launch_label_max(const int32_t* const* dlabels, int32_t k, int64_t n, int32_t* maxlab,
@@ -55,9 +69,21 @@ void launch_scan(const int32_t* in, int32_t* out, int64_t len, int32_t* tmp, hip
 int64_t scan_tmp_elems(int64_t len);
 void launch_label_counts(const int32_t* scan, const int64_t* loff, int32_t k, int32_t* Lc,
                          hipStream_t st);
+// fmap[loff[i] + x] = dense id of raw label x of partition i (where present)
+void launch_label_ids(const int32_t* scan, const int64_t* loff, int32_t k, int64_t max_span,
+                      int32_t* fmap, hipStream_t st);
 void launch_label_transpose(const int32_t* const* dlabels, int32_t k, int64_t n,
-                            const int64_t* loff, const int32_t* scan, int32_t* Lvm,
+                            const int64_t* loff, const int32_t* fmap, int32_t* Lvm,
                             hipStream_t st);
+// Label alignment from a blocked table: amap[poff[i] + l] = new id of dense
+// label l of partition i, L2[i] = new id bound of partition i.
+void launch_align(const Tables& blocked, int32_t k, int32_t K0, int32_t maxL,
+                  const int64_t* poff, int64_t total_labels, uint64_t* win, int32_t* home,
+                  uint64_t* key, int32_t* extra, int32_t* rank, int32_t* scan_tmp,
+                  int32_t* amap, int32_t* L2, hipStream_t st);
+void launch_fmap_update(const int32_t* scan, const int64_t* loff, const int64_t* poff,
+                        const int32_t* amap, int32_t k, int64_t max_span, int32_t* fmap,
+                        hipStream_t st);
 void launch_cluster_mark(const int32_t* init, int64_t n, int32_t* flags, int32_t* err,
                          hipStream_t st);
 void launch_cluster_assign(const int32_t* init, int64_t n, const int32_t* cmap, int32_t* C,
@@ -66,9 +92,10 @@ void launch_iota(int32_t* a, int64_t n, hipStream_t st);
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st);
 void launch_fill_u64(uint64_t* a, int64_t n, uint64_t v, hipStream_t st);
 void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t* loff,
-                  const int32_t* scan, int64_t n, int32_t k, int32_t K0, Tables t, int32_t* s,
+                  const int32_t* fmap, int64_t n, int32_t k, int32_t K0, Tables t,
                   hipStream_t st);
-void launch_objective0(const Tables& t, int32_t k, int32_t K0, const int32_t* s,
+void launch_sizes(const int32_t* C, int64_t n, int32_t K0, int32_t* s, hipStream_t st);
+void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, const int32_t* s,
                        int64_t total_entries,
                        int64_t* acc /* 3 int64: sum s^2, sum hist^2, sum N^2 */,
                        hipStream_t st);
@@ -102,7 +129,10 @@ struct PassArgs {
 
 int score_lanes_auto(int32_t k);
 bool score_lanes_ok(int lanes);
-void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, hipStream_t st);
+// Enqueue one pass; when the events are given they bracket the scoring
+// kernel on the same stream.
+void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, hipStream_t st,
+                  hipEvent_t score_begin = nullptr, hipEvent_t score_end = nullptr);
 void launch_ctl_init(Ctl* ctl, const int64_t* acc, int32_t k, int32_t max_rounds,
                      int64_t* trace, hipStream_t st);
 

@@ -77,30 +77,30 @@ __device__ inline int32_t wave_sum32(int32_t x) {
 // repeated group minima, so duplicates vanish and ties resolve to the
 // smallest id without any sort.
 // ---------------------------------------------------------------------------
-constexpr int KR = 4;
+constexpr int kMaxLdsPart = 256;  // partitions whose table geometry sits in LDS
 
 template <int G>
 __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
   if (a.ctl->done) return;
-  constexpr int R = (128 / G) > 1 ? (128 / G) : 1;
+  constexpr int R = (128 / G) < 16 ? ((128 / G) > 1 ? (128 / G) : 1) : 16;
+  constexpr int KR = (64 / G) > 1 ? (64 / G) : 1;  // labels held per lane
   constexpr int32_t kInf = 0x7fffffff;
+  __shared__ int64_t s_toff[kMaxLdsPart];
+  __shared__ int32_t s_L[kMaxLdsPart];
   const int lane = threadIdx.x & (G - 1);
   const int64_t group = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
   const int64_t ngroups = ((int64_t)gridDim.x * kBlock) / G;
   const int32_t k = a.k;
   const bool kfits = k <= KR * G;
-
-  int64_t toff[KR];
-  int32_t Lp[KR];
-#pragma unroll
-  for (int t = 0; t < KR; ++t) {
-    int i = lane + t * G;
-    toff[t] = i < k ? a.t.toff[i] : 0;
-    Lp[t] = i < k ? a.t.L[i] : 0;
+  for (int i = threadIdx.x; i < k && i < kMaxLdsPart; i += kBlock) {
+    s_toff[i] = a.t.interleaved ? 0 : a.t.toff[i];  // no offsets when interleaved
+    s_L[i] = a.t.L[i];
   }
+  __syncthreads();
+  const bool lds_geom = k <= kMaxLdsPart;
 
   int64_t evals = 0;
-  int32_t nprop = 0;
+  int32_t nprop = 0, boundary = 0;
   for (int64_t v = group; v < a.n; v += ngroups) {
     const int32_t cv = a.C[v];
     const int64_t beg = a.row_ptr[v], end = a.row_ptr[v + 1];
@@ -118,24 +118,44 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
         }
       }
     }
+    // the label row is read only once the vertex has a candidate: interior
+    // vertices (every neighbour in their own cluster) never touch it
     const int32_t* row = a.Lvm + v * k;
     int32_t lab[KR];
-    if (kfits) {
-#pragma unroll
-      for (int t = 0; t < KR; ++t) {
-        int i = lane + t * G;
-        lab[t] = i < k ? row[i] : 0;
-      }
-    }
-    // S_y(v) summed over the group's lanes
-    auto agree = [&](int32_t y) -> int32_t {
-      int32_t sum = 0;
-      if (kfits) {
+    bool have_row = false;
+    auto load_row = [&]() {
+      if (kfits && !have_row) {
 #pragma unroll
         for (int t = 0; t < KR; ++t) {
           int i = lane + t * G;
-          if (i < k) sum += a.t.N[toff[t] + (int64_t)y * Lp[t] + lab[t]];
+          lab[t] = i < k ? row[i] : 0;
         }
+      }
+      have_row = true;
+    };
+    // S_y(v) summed over the group's lanes
+    auto agree = [&](int32_t y) -> int32_t {
+      int32_t sum = 0;
+      if (a.t.interleaved) {
+        const int64_t base = (int64_t)y * a.t.Lmax;
+        if (kfits) {
+#pragma unroll
+          for (int t = 0; t < KR; ++t) {
+            int i = lane + t * G;
+            if (i < k) sum += a.t.N[(base + lab[t]) * k + i];
+          }
+        } else {
+          for (int i = lane; i < k; i += G) sum += a.t.N[(base + row[i]) * k + i];
+        }
+      } else if (kfits) {  // implies lds_geom
+#pragma unroll
+        for (int t = 0; t < KR; ++t) {
+          int i = lane + t * G;
+          if (i < k) sum += a.t.N[s_toff[i] + (int64_t)y * s_L[i] + lab[t]];
+        }
+      } else if (lds_geom) {
+        for (int i = lane; i < k; i += G)
+          sum += a.t.N[s_toff[i] + (int64_t)y * s_L[i] + row[i]];
       } else {
         for (int i = lane; i < k; i += G)
           sum += a.t.N[a.t.toff[i] + (int64_t)y * a.t.L[i] + row[i]];
@@ -161,7 +181,10 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
       }
       m = group_min<G>(m);
       if (m == kInf) break;
-      if (s_own < 0) s_own = agree(cv);
+      if (s_own < 0) {
+        load_row();
+        s_own = agree(cv);
+      }
       const int64_t sx = agree(m);
       int64_t d = 2 * (s_own - sx) + (int64_t)k * ((int64_t)a.s[m] - sc - 1);
       if (a.literal) d += k;
@@ -179,6 +202,7 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
     }
     if (lane == 0) {
       evals += ncand;
+      boundary += ncand > 0;
       const bool p = ncand > 0 && bestd < 0;
       a.prop[v] = p ? bestx : kNone;
       if (p) {
@@ -189,9 +213,11 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
   }
   evals = wave_sum64(evals);
   nprop = wave_sum32(nprop);
+  boundary = wave_sum32(boundary);
   if ((threadIdx.x & 63) == 0) {
     if (evals) atomicAdd((unsigned long long*)&a.ctl->pass_evals, (unsigned long long)evals);
     if (nprop) atomicAdd(&a.ctl->nprop, nprop);
+    if (boundary) atomicAdd((unsigned long long*)&a.ctl->boundary, (unsigned long long)boundary);
   }
 }
 
@@ -221,11 +247,9 @@ __device__ inline int64_t move_counts(const PassArgs& a, int64_t v, int32_t from
   int64_t acc = 0;
   const int32_t* row = a.Lvm + v * a.k;
   for (int i = lane; i < a.k; i += 64) {
-    const int64_t off = a.t.toff[i];
-    const int32_t Li = a.t.L[i];
     const int32_t l = row[i];
-    int32_t o1 = atomicAdd(&a.t.N[off + (int64_t)to * Li + l], d);
-    int32_t o2 = atomicAdd(&a.t.N[off + (int64_t)from * Li + l], -d);
+    int32_t o1 = atomicAdd(&a.t.N[cell(a.t, i, to, l)], d);
+    int32_t o2 = atomicAdd(&a.t.N[cell(a.t, i, from, l)], -d);
     acc += 2 * (int64_t)o1 * d + 1 - 2 * (int64_t)o2 * d + 1;
   }
   if (lane == 0) {
@@ -377,7 +401,9 @@ void launch_ctl_init(Ctl* ctl, const int64_t* acc, int32_t k, int32_t max_rounds
   k_ctl_init<<<1, 1, 0, st>>>(ctl, acc, k, max_rounds, trace);
 }
 
-void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, hipStream_t st) {
+void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, hipStream_t st,
+                  hipEvent_t score_begin, hipEvent_t score_end) {
+  if (score_begin) (void)hipEventRecord(score_begin, st);
   switch (lanes) {
     case 4: launch_score<4>(a, grid_score, st); break;
     case 8: launch_score<8>(a, grid_score, st); break;
@@ -385,6 +411,7 @@ void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, 
     case 32: launch_score<32>(a, grid_score, st); break;
     default: launch_score<64>(a, grid_score, st); break;
   }
+  if (score_end) (void)hipEventRecord(score_end, st);
   k_begin<<<1, 1, 0, st>>>(a.ctl);
   k_apply<kApplyAll><<<grid_apply, kBlock, 0, st>>>(a);
   k_decide<<<1, 1, 0, st>>>(a.ctl);

@@ -148,22 +148,42 @@ __global__ void k_label_counts(const int32_t* __restrict__ scan, const int64_t* 
   if (i < k) Lc[i] = scan[loff[i + 1]] - scan[loff[i]];
 }
 
-// Dense labels, transposed to vertex-major rows: Lvm[v * k + i] = id of
+// fmap[loff[i] + x] = dense id of label x of partition i, for present labels
+__global__ __launch_bounds__(kBlock) void k_label_ids(const int32_t* __restrict__ scan,
+                                                      const int64_t* __restrict__ loff,
+                                                      int32_t* __restrict__ fmap) {
+  const int i = blockIdx.y;
+  const int64_t b = loff[i], e = loff[i + 1];
+  const int32_t base = scan[b];
+  for (int64_t p = b + gtid(); p < e; p += gstride()) fmap[p] = scan[p] - base;
+}
+
+// Relabel present labels through the alignment map.
+__global__ __launch_bounds__(kBlock) void k_fmap_update(const int32_t* __restrict__ scan,
+                                                        const int64_t* __restrict__ loff,
+                                                        const int64_t* __restrict__ poff,
+                                                        const int32_t* __restrict__ amap,
+                                                        int32_t* __restrict__ fmap) {
+  const int i = blockIdx.y;
+  const int64_t b = loff[i], e = loff[i + 1];
+  const int32_t* am = amap + poff[i];
+  for (int64_t p = b + gtid(); p < e; p += gstride())
+    if (scan[p + 1] > scan[p]) fmap[p] = am[fmap[p]];
+}
+
+// Label ids, transposed to vertex-major rows: Lvm[v * k + i] = id of
 // P_i(v).  A workgroup moves a tile of tv vertices x k partitions through
 // LDS so that both the partition-major reads and the row writes coalesce.
 __global__ __launch_bounds__(kBlock) void k_label_transpose(
     const int32_t* const* __restrict__ labels, int32_t k, int64_t n,
-    const int64_t* __restrict__ loff, const int32_t* __restrict__ scan, int tv,
+    const int64_t* __restrict__ loff, const int32_t* __restrict__ fmap, int tv,
     int32_t* __restrict__ Lvm) {
   extern __shared__ int32_t tile[];  // [k][tv + 1]
   const int64_t v0 = (int64_t)blockIdx.x * tv;
   const int rows = min((int64_t)tv, n - v0);
   for (int f = threadIdx.x; f < tv * k; f += kBlock) {
     int vv = f % tv, i = f / tv;
-    if (vv < rows) {
-      int64_t off = loff[i];
-      tile[i * (tv + 1) + vv] = scan[off + labels[i][v0 + vv]] - scan[off];
-    }
+    if (vv < rows) tile[i * (tv + 1) + vv] = fmap[loff[i] + labels[i][v0 + vv]];
   }
   __syncthreads();
   int32_t* dst = Lvm + v0 * k;
@@ -214,18 +234,17 @@ __global__ __launch_bounds__(kBlock) void k_fill_u64(uint64_t* __restrict__ a, i
 constexpr int kLdsHist = 16384;  // int32 entries privatised in LDS (64 KiB)
 
 // Workgroup (b, i) counts the pairs (C(v), P_i(v)) of its vertex range for
-// partition i.  When partition i's table fits kLdsHist entries the counts
-// are gathered in LDS and flushed once; otherwise they go straight to the
-// global table.
+// partition i.  When partition i's K0 x L[i] slice fits kLdsHist entries the
+// counts are gathered in LDS and flushed once; otherwise they go straight to
+// the global table.
 __global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
                                                   const int32_t* const* __restrict__ labels,
                                                   const int64_t* __restrict__ loff,
-                                                  const int32_t* __restrict__ scan, int64_t n,
+                                                  const int32_t* __restrict__ fmap, int64_t n,
                                                   int32_t K0, Tables t) {
   __shared__ int32_t h[kLdsHist];
   const int i = blockIdx.y;
   const int32_t Li = t.L[i];
-  int32_t* Ni = t.N + t.toff[i];
   const int64_t entries = (int64_t)K0 * Li;
   const bool lds = entries <= kLdsHist;
   if (lds) {
@@ -235,19 +254,21 @@ __global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
   const int64_t per = (n + gridDim.x - 1) / gridDim.x;
   const int64_t v0 = (int64_t)blockIdx.x * per;
   const int64_t v1 = min(n, v0 + per);
-  // partition-major input labels (coalesced) mapped to dense ids
+  // partition-major input labels (coalesced) mapped to their ids
   const int32_t* p = labels[i];
-  const int32_t* map = scan + loff[i];
-  const int32_t base = map[0];
+  const int32_t* map = fmap + loff[i];
   for (int64_t v = v0 + threadIdx.x; v < v1; v += kBlock) {
-    int64_t idx = (int64_t)C[v] * Li + (map[p[v]] - base);
-    if (lds) atomicAdd(&h[idx], 1);
-    else atomicAdd(&Ni[idx], 1);
+    const int32_t x = C[v], l = map[p[v]];
+    if (lds) atomicAdd(&h[x * Li + l], 1);
+    else atomicAdd(&t.N[cell(t, i, x, l)], 1);
   }
   if (lds) {
     __syncthreads();
     for (int j = threadIdx.x; j < entries; j += kBlock)
-      if (h[j]) atomicAdd(&Ni[j], h[j]);
+      if (h[j]) {
+        const int32_t x = j / Li;
+        atomicAdd(&t.N[cell(t, i, x, j - x * Li)], h[j]);
+      }
   }
 }
 
@@ -286,11 +307,10 @@ __global__ __launch_bounds__(kBlock) void k_hist_sumsq(Tables t, int32_t K0,
                                                        int64_t* __restrict__ acc) {
   const int i = blockIdx.y;
   const int32_t Li = t.L[i];
-  const int32_t* Ni = t.N + t.toff[i];
   int64_t s = 0;
   for (int64_t l = gtid(); l < Li; l += gstride()) {
     int64_t h = 0;
-    for (int32_t x = 0; x < K0; ++x) h += Ni[(int64_t)x * Li + l];
+    for (int32_t x = 0; x < K0; ++x) h += t.N[cell(t, i, x, (int32_t)l)];
     s += h * h;
   }
   s = block_sum<int64_t>(s);
@@ -348,6 +368,66 @@ __global__ __launch_bounds__(kBlock) void k_canonical_write(const int32_t* __res
   for (int64_t v = gtid(); v < n; v += gstride()) out[v] = rank[first[in[v]]];
 }
 
+// ---- label alignment -----------------------------------------------------------
+// Each label l of partition i has a home: the consensus cluster holding most
+// of its vertices (ties to the smallest cluster).  Among the labels homed at
+// cluster x, the largest (ties to the smallest label) takes id x; the others
+// take ids K0, K0 + 1, ... in label order.  Any injective relabelling leaves
+// every count unchanged; this one puts a vertex's labels and its cluster
+// side by side in the interleaved table.
+__global__ __launch_bounds__(kBlock) void k_align_home(Tables b, int32_t K0,
+                                                       const int64_t* __restrict__ poff,
+                                                       uint64_t* __restrict__ win,
+                                                       int32_t* __restrict__ home,
+                                                       uint64_t* __restrict__ key) {
+  const int i = blockIdx.y;
+  const int32_t Li = b.L[i];
+  for (int64_t l = gtid(); l < Li; l += gstride()) {
+    int32_t bx = 0, bc = -1;
+    for (int32_t x = 0; x < K0; ++x) {
+      const int32_t c = b.N[cell(b, i, x, (int32_t)l)];
+      if (c > bc) {
+        bc = c;
+        bx = x;
+      }
+    }
+    const uint64_t kk = ((uint64_t)(uint32_t)bc << 32) | (uint64_t)(0xffffffffu - (uint32_t)l);
+    home[poff[i] + l] = bx;
+    key[poff[i] + l] = kk;
+    atomicMax((unsigned long long*)&win[(int64_t)i * K0 + bx], (unsigned long long)kk);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_align_extra(const int32_t* __restrict__ L, int32_t K0,
+                                                        const int64_t* __restrict__ poff,
+                                                        const uint64_t* __restrict__ win,
+                                                        const int32_t* __restrict__ home,
+                                                        const uint64_t* __restrict__ key,
+                                                        int32_t* __restrict__ extra) {
+  const int i = blockIdx.y;
+  for (int64_t l = gtid(); l < L[i]; l += gstride()) {
+    const int64_t p = poff[i] + l;
+    extra[p] = win[(int64_t)i * K0 + home[p]] != key[p];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_align_assign(const int32_t* __restrict__ L,
+                                                         int32_t K0,
+                                                         const int64_t* __restrict__ poff,
+                                                         const int32_t* __restrict__ home,
+                                                         const int32_t* __restrict__ extra,
+                                                         const int32_t* __restrict__ rank,
+                                                         int32_t* __restrict__ amap,
+                                                         int32_t* __restrict__ L2) {
+  const int i = blockIdx.y;
+  const int64_t b = poff[i];
+  for (int64_t l = gtid(); l < L[i]; l += gstride()) {
+    const int64_t p = b + l;
+    amap[p] = extra[p] ? K0 + (rank[p] - rank[b]) : home[p];
+  }
+  if (gtid() == 0) L2[i] = K0 + (rank[poff[i + 1]] - rank[b]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_dense_map(const int32_t* __restrict__ in, int64_t n,
                                                       const int32_t* __restrict__ scan,
                                                       int32_t* __restrict__ out) {
@@ -386,14 +466,39 @@ void launch_label_counts(const int32_t* scan, const int64_t* loff, int32_t k, in
   k_label_counts<<<grid_for(k, kBlock), kBlock, 0, st>>>(scan, loff, k, Lc);
 }
 
+void launch_label_ids(const int32_t* scan, const int64_t* loff, int32_t k, int64_t max_span,
+                      int32_t* fmap, hipStream_t st) {
+  dim3 g(grid_for(max_span, kBlock, 256), k);
+  k_label_ids<<<g, kBlock, 0, st>>>(scan, loff, fmap);
+}
+
+void launch_fmap_update(const int32_t* scan, const int64_t* loff, const int64_t* poff,
+                        const int32_t* amap, int32_t k, int64_t max_span, int32_t* fmap,
+                        hipStream_t st) {
+  dim3 g(grid_for(max_span, kBlock, 256), k);
+  k_fmap_update<<<g, kBlock, 0, st>>>(scan, loff, poff, amap, fmap);
+}
+
+void launch_align(const Tables& blocked, int32_t k, int32_t K0, int32_t maxL,
+                  const int64_t* poff, int64_t total_labels, uint64_t* win, int32_t* home,
+                  uint64_t* key, int32_t* extra, int32_t* rank, int32_t* scan_tmp,
+                  int32_t* amap, int32_t* L2, hipStream_t st) {
+  dim3 g(grid_for(maxL, kBlock, 256), k);
+  k_fill_u64<<<grid_for((int64_t)k * K0, kBlock, 2048), kBlock, 0, st>>>(win, (int64_t)k * K0, 0ull);
+  k_align_home<<<g, kBlock, 0, st>>>(blocked, K0, poff, win, home, key);
+  k_align_extra<<<g, kBlock, 0, st>>>(blocked.L, K0, poff, win, home, key, extra);
+  launch_scan(extra, rank, total_labels, scan_tmp, st);
+  k_align_assign<<<g, kBlock, 0, st>>>(blocked.L, K0, poff, home, extra, rank, amap, L2);
+}
+
 void launch_label_transpose(const int32_t* const* dlabels, int32_t k, int64_t n,
-                            const int64_t* loff, const int32_t* scan, int32_t* Lvm,
+                            const int64_t* loff, const int32_t* fmap, int32_t* Lvm,
                             hipStream_t st) {
   int tv = 64;
   while (tv > 1 && (int64_t)(tv + 1) * k * 4 > 48 * 1024) tv >>= 1;
   size_t lds = (size_t)(tv + 1) * k * sizeof(int32_t);
   int64_t nb = (n + tv - 1) / tv;
-  k_label_transpose<<<(unsigned)nb, kBlock, lds, st>>>(dlabels, k, n, loff, scan, tv, Lvm);
+  k_label_transpose<<<(unsigned)nb, kBlock, lds, st>>>(dlabels, k, n, loff, fmap, tv, Lvm);
 }
 
 void launch_cluster_mark(const int32_t* init, int64_t n, int32_t* flags, int32_t* err,
@@ -419,7 +524,7 @@ void launch_fill_u64(uint64_t* a, int64_t n, uint64_t v, hipStream_t st) {
 }
 
 void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t* loff,
-                  const int32_t* scan, int64_t n, int32_t k, int32_t K0, Tables t, int32_t* s,
+                  const int32_t* fmap, int64_t n, int32_t k, int32_t K0, Tables t,
                   hipStream_t st) {
   // enough workgroups per partition to fill the chip, few enough that the
   // LDS flush stays small next to the counting
@@ -427,16 +532,19 @@ void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t
   if (per_part > 64) per_part = 64;
   if (per_part < 1) per_part = 1;
   dim3 g((unsigned)per_part, k);
-  k_build<<<g, kBlock, 0, st>>>(C, dlabels, loff, scan, n, K0, t);
+  k_build<<<g, kBlock, 0, st>>>(C, dlabels, loff, fmap, n, K0, t);
+}
+
+void launch_sizes(const int32_t* C, int64_t n, int32_t K0, int32_t* s, hipStream_t st) {
   k_sizes<<<grid_for(n, kBlock * 16, 512), kBlock, 0, st>>>(C, n, K0, s);
 }
 
-void launch_objective0(const Tables& t, int32_t k, int32_t K0, const int32_t* s,
+void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, const int32_t* s,
                        int64_t total_entries, int64_t* acc, hipStream_t st) {
   // acc[0] += sum_x s_x^2; acc[1] += sum_i sum_l |P_i l|^2;
   // acc[2] += sum_i sum_(x,l) N_i(x,l)^2 over all `total_entries` table cells
   k_sumsq<<<grid_for(K0, kBlock, 1024), kBlock, 0, st>>>(s, K0, acc);
-  dim3 g(64, k);
+  dim3 g(grid_for(maxL, kBlock, 64), k);
   k_hist_sumsq<<<g, kBlock, 0, st>>>(t, K0, acc + 1);
   k_sumsq<<<grid_for(total_entries, kBlock, 2048), kBlock, 0, st>>>(t.N, total_entries, acc + 2);
 }
