@@ -52,6 +52,12 @@ extern "C" {
                                gain) */
 #define MCC_F_PROFILE 0x8u  /* time every scoring kernel with HIP events on the
                                call's stream (stats->ms_score) */
+#define MCC_F_ARC_CACHE 0x10u /* keep a per-arc copy of the neighbour's cluster,
+                                 updated through in-arc lists when vertices
+                                 move, instead of gathering clusters every
+                                 pass (costs nnz * 8 bytes and a list build;
+                                 pays off with many passes; a tuning knob,
+                                 results do not depend on it) */
 
 /* CSR graph: row_ptr[n + 1] (int64, row_ptr[0] = 0, non-decreasing,
  * row_ptr[n] = nnz) and col[nnz] (int32 vertex ids in [0, n)).  Arcs are
@@ -74,9 +80,9 @@ typedef struct {
                          back to the conflict-free subset, objective after
                          the pass); the final pass that finds no move records
                          (0, 0, 0, objective) */
-  int32_t lanes;      /* lanes that score one vertex: 0 = automatic, else one
-                         of 4, 8, 16, 32, 64 (a tuning knob; results do not
-                         depend on it) */
+  int32_t lanes;      /* scoring kernel: 0 = tiled scorer (default), else one
+                         of 4, 8, 16, 32, 64 lanes per vertex for the group
+                         scorer (a tuning knob; results do not depend on it) */
   int32_t reserved;
   /* out */
   int32_t passes;          /* scoring passes, including the final one that
@@ -96,7 +102,7 @@ typedef struct {
                               least one candidate (their label rows are read) */
   float ms_score;          /* with MCC_F_PROFILE: summed duration of the
                               scoring kernels of the executed passes */
-  int32_t lanes_used;      /* lanes per vertex the scoring kernel ran with */
+  int32_t lanes_used;      /* the `lanes` the scoring ran with (0 = tiled) */
 } mcc_stats;
 
 /*
@@ -129,7 +135,8 @@ typedef struct {
  *
  * The result (out and every stats field except the timings) is a
  * deterministic function of the inputs and equals the plain sequential
- * definition bit for bit.  Limits: n * k < 2^31; the contingency tables
+ * definition bit for bit.  Limits: n * k < 2^31; nnz < 2^31 - 1 (else
+ * MCC_ENOTSUP); the contingency tables
  * (consensus cluster x label, per partition) must fit the library's table
  * budget, else MCC_ENOTSUP.
  */

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(PKG, "libmcc.so")
 
 MCC_OK, MCC_EINVAL, MCC_EGRAPH, MCC_ENOMEM, MCC_EDEVICE, MCC_ENOTSUP = 0, -1, -2, -3, -4, -5
 MCC_F_VALIDATE, MCC_F_TRACE, MCC_F_LITERAL, MCC_F_PROFILE = 0x1, 0x2, 0x4, 0x8
+MCC_F_ARC_CACHE = 0x10
 
 # every function include/mcc.h declares
 EXPORTS = ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize", "mcc_strerror")

@@ -377,6 +377,7 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
   if ((flags & MCC_F_TRACE) && !stats->trace) return MCC_EINVAL;
   if ((int64_t)k * n >= ((int64_t)1 << 31)) return MCC_EINVAL;
   if (!labels) return MCC_EINVAL;
+  if (g->nnz >= ((int64_t)1 << 31) - 1) return MCC_ENOTSUP;  // 32-bit arc positions
   if (stats) {
     stats->passes = stats->converged = stats->fallback_rounds = stats->clusters = 0;
     stats->moves = stats->candidate_evals = stats->objective_init = stats->objective = 0;
@@ -426,6 +427,25 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
     launch_fill_u64(owner, S.K0, ~0ull, st);
     int32_t* prop = ar.get<int32_t>(n);
     int64_t* dprop = ar.get<int64_t>(n);
+    int32_t* heavy = ar.get<int32_t>(n);
+    // arc clusters and in-arc lists, on request
+    const int64_t nnz = g->nnz;
+    int32_t* in_ptr = nullptr;
+    int32_t* in_pos = nullptr;
+    int32_t* ac = nullptr;
+    if (flags & MCC_F_ARC_CACHE) {
+      in_ptr = ar.get<int32_t>(n + 1);
+      int32_t* indeg = ar.get<int32_t>(n + 1);
+      launch_fill_i32(indeg, n + 1, 0, st);
+      launch_in_degree(g->col, nnz, indeg, st);
+      int32_t* stmp = ar.get<int32_t>(scan_tmp_elems(n));
+      launch_scan(indeg, in_ptr, n, stmp, st);
+      launch_copy_i32(in_ptr, indeg, n, st);  // cursors
+      in_pos = ar.get<int32_t>(nnz);
+      launch_in_fill(g->col, nnz, indeg, in_pos, st);
+      ac = ar.get<int32_t>(nnz);
+      launch_arc_clusters(g->col, nnz, S.C, ac, st);
+    }
 
     PassArgs a;
     a.ctl = ctl;
@@ -441,11 +461,19 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
     a.prop = prop;
     a.dprop = dprop;
     a.owner = owner;
+    a.heavy = heavy;
+    a.ac = ac;
+    a.in_ptr = in_ptr;
+    a.in_pos = in_pos;
+    a.cells = S.total;
+    if (S.total + S.K0 >= ((int64_t)1 << 31)) throw Status{MCC_ENOTSUP};  // 32-bit update keys
 
-    const int lanes = lanes_req ? lanes_req : score_lanes_auto(k);
+    // the tiled scorer packs cluster ids in 24 bits
+    const int lanes = (lanes_req == 0 && S.K0 >= (1 << 24)) ? 64 : lanes_req;
     const int sms = device_sms();
-    const int64_t groups_needed = (n * lanes + kBlock - 1) / kBlock;
-    const int grid_score = (int)std::max<int64_t>(1, std::min<int64_t>(groups_needed, sms * 8));
+    const int64_t blocks_needed =
+        lanes ? (n * lanes + kBlock - 1) / kBlock : (n + kBlock - 1) / kBlock;
+    const int grid_score = (int)std::max<int64_t>(1, std::min<int64_t>(blocks_needed, sms * 8));
     const int grid_apply =
         (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, sms * 4));
 

@@ -31,6 +31,8 @@ struct Ctl {
   int64_t O;                // current objective sum_i Mirkin(C, P_i)
   int64_t moves;            // committed moves in all passes
   int64_t boundary;         // vertices with a candidate, summed over passes
+  int32_t heavy_count;      // vertices deferred by the tiled scorer this pass
+  int32_t pad2;
   int64_t* trace;           // device int64[max_rounds * 4] or null
 };
 
@@ -99,6 +101,14 @@ void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, con
                        int64_t total_entries,
                        int64_t* acc /* 3 int64: sum s^2, sum hist^2, sum N^2 */,
                        hipStream_t st);
+// In-arc lists: in_ptr (exclusive scan of in-degrees, n + 1) and in_pos
+// (arc positions grouped by head vertex); ac[j] = C[col[j]].
+void launch_in_degree(const int32_t* col, int64_t nnz, int32_t* indeg, hipStream_t st);
+void launch_in_fill(const int32_t* col, int64_t nnz, int32_t* cursor, int32_t* in_pos,
+                    hipStream_t st);
+void launch_arc_clusters(const int32_t* col, int64_t nnz, const int32_t* C, int32_t* ac,
+                         hipStream_t st);
+void launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t st);
 void launch_validate_csr(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
                          int32_t* err, hipStream_t st);
 void launch_finish(const int32_t* C, const int32_t* rawid, int64_t n, int32_t* out,
@@ -125,9 +135,43 @@ struct PassArgs {
   int32_t* prop;      // proposed target cluster, -1 none; fallback marks
   int64_t* dprop;     // gain of the proposal
   uint64_t* owner;    // per cluster, fallback owners
+  int32_t* heavy;     // [n] vertices the tiled scorer defers to the group scorer
+  // ac[j] = C[col[j]]: the cluster at the head of every arc, kept current by
+  // rewriting the in-arcs of each vertex that moves (in_pos[in_ptr[u] ..
+  // in_ptr[u + 1]) are the arcs pointing at u), so that scoring streams
+  // arcs instead of gathering clusters
+  int32_t* ac;
+  const int32_t* in_ptr;
+  const int32_t* in_pos;
+  int64_t cells;      // table cells (keys >= cells address cluster sizes)
 };
 
-int score_lanes_auto(int32_t k);
+// Exclusive scan of one value per thread over a kBlock-thread workgroup;
+// *total receives the sum.  Contains barriers: call from all threads.
+__device__ inline int32_t block_exclusive_scan(int32_t x, int32_t* total) {
+  __shared__ int32_t wsum[kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int32_t v = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int32_t y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
+  }
+  if (lane == 63) wsum[w] = v;
+  __syncthreads();
+  int32_t off = 0, tot = 0;
+#pragma unroll
+  for (int j = 0; j < kBlock / 64; ++j) {
+    if (j < w) off += wsum[j];
+    tot += wsum[j];
+  }
+  __syncthreads();
+  *total = tot;
+  return off + v - x;
+}
+
+// lanes 0: tiled scorer (with the group scorer for deferred vertices);
+// 4..64: group scorer with that many lanes per vertex.
 bool score_lanes_ok(int lanes);
 // Enqueue one pass; when the events are given they bracket the scoring
 // kernel on the same stream.

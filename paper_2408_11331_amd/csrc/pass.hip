@@ -79,9 +79,12 @@ __device__ inline int32_t wave_sum32(int32_t x) {
 // ---------------------------------------------------------------------------
 constexpr int kMaxLdsPart = 256;  // partitions whose table geometry sits in LDS
 
-template <int G>
+template <int G, bool LIST>
 __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
   if (a.ctl->done) return;
+  // LIST: score only the vertices the tiled scorer deferred
+  const int64_t count = LIST ? (int64_t)a.ctl->heavy_count : a.n;
+  if (LIST && count == 0) return;
   constexpr int R = (128 / G) < 16 ? ((128 / G) > 1 ? (128 / G) : 1) : 16;
   constexpr int KR = (64 / G) > 1 ? (64 / G) : 1;  // labels held per lane
   constexpr int32_t kInf = 0x7fffffff;
@@ -101,7 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
 
   int64_t evals = 0;
   int32_t nprop = 0, boundary = 0;
-  for (int64_t v = group; v < a.n; v += ngroups) {
+  for (int64_t idx = group; idx < count; idx += ngroups) {
+    const int64_t v = LIST ? (int64_t)a.heavy[idx] : idx;
     const int32_t cv = a.C[v];
     const int64_t beg = a.row_ptr[v], end = a.row_ptr[v + 1];
     const bool fits = end - beg <= (int64_t)G * R;
@@ -112,9 +116,9 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
         int64_t j = beg + r * G + lane;
         x[r] = kInf;
         if (j < end) {
-          int32_t u = a.col[j];
-          int32_t cu = a.C[u];
-          if (u != v && cu != cv) x[r] = cu;
+          // a self-loop points at v's own cluster and drops out with it
+          const int32_t cu = a.ac ? a.ac[j] : a.C[a.col[j]];
+          if (cu != cv) x[r] = cu;
         }
       }
     }
@@ -173,9 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
         for (int r = 0; r < R; ++r) m = min(m, x[r]);
       } else {
         for (int64_t j = beg + lane; j < end; j += G) {
-          int32_t u = a.col[j];
-          if (u == v) continue;
-          int32_t cu = a.C[u];
+          const int32_t cu = a.ac ? a.ac[j] : a.C[a.col[j]];
           if (cu != cv && cu > last && cu < m) m = cu;
         }
       }
@@ -210,6 +212,235 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
         ++nprop;
       }
     }
+  }
+  evals = wave_sum64(evals);
+  nprop = wave_sum32(nprop);
+  boundary = wave_sum32(boundary);
+  if ((threadIdx.x & 63) == 0) {
+    if (evals) atomicAdd((unsigned long long*)&a.ctl->pass_evals, (unsigned long long)evals);
+    if (nprop) atomicAdd(&a.ctl->nprop, nprop);
+    if (boundary) atomicAdd((unsigned long long*)&a.ctl->boundary, (unsigned long long)boundary);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tiled scorer.  A workgroup owns a tile of kBlock consecutive vertices:
+//  1. the tile's row offsets and clusters go to LDS;
+//  2. its arcs are walked in chunks, every thread taking kArcChunk / kBlock
+//     arcs with independent loads; each arc whose head lies in another
+//     cluster inserts the key (tail, head cluster) into a tile-wide LDS hash
+//     set, and the first insertion of a key appends the cluster to the
+//     tail's candidate list (a self-loop points at the own cluster and drops
+//     out with it);
+//  3. the (vertex, cluster) pairs of the tile's boundary vertices, own
+//     cluster first, form a flat list that groups of kProbeLanes lanes probe
+//     four pairs at a time, lanes spread over the partitions;
+//  4. one thread per vertex takes the smallest (gain, cluster id).
+// Vertices with more than kMaxCand candidate clusters, or whose keys find no
+// slot in the set, are deferred to a list the group scorer finishes in the
+// same pass, so results never depend on these capacities.
+// ---------------------------------------------------------------------------
+constexpr int kArcChunk = 1024;
+constexpr int kMaxCand = 8;
+constexpr int kSetSlots = 2048;
+constexpr int kSetProbe = 64;
+constexpr int kPairMax = kBlock * (1 + kMaxCand);
+constexpr int kProbeLanes = 16;
+constexpr int kProbeRegs = 64 / kProbeLanes;  // labels per lane when k <= 64
+constexpr int kProbeBatch = 4;
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_score_tile(PassArgs a) {
+  if (a.ctl->done) return;
+  __shared__ int32_t s_off[kBlock + 1];
+  __shared__ int32_t s_c[kBlock];
+  __shared__ int32_t s_nc[kBlock];
+  __shared__ int32_t s_cand[kMaxCand * kBlock];  // [slot][vertex]
+  __shared__ int32_t s_pv[kPairMax];             // (vertex << 4) | slot, slot 0 = own
+  __shared__ int32_t s_buf[kPairMax];            // set keys, then agreement sums
+  const int t = threadIdx.x;
+  const int32_t k = a.k;
+  const bool kfits = k <= kProbeRegs * kProbeLanes;
+  const int g = t / kProbeLanes, lane = t % kProbeLanes;
+  int64_t evals = 0;
+  int32_t nprop = 0, boundary = 0;
+  const int64_t ntiles = (a.n + kBlock - 1) / kBlock;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t v0 = tile * kBlock;
+    const int nv = (int)min((int64_t)kBlock, a.n - v0);
+    const int64_t a0 = a.row_ptr[v0];
+    for (int j = t; j <= nv; j += kBlock) s_off[j] = (int32_t)(a.row_ptr[v0 + j] - a0);
+    s_c[t] = t < nv ? a.C[v0 + t] : -1;
+    s_nc[t] = 0;
+    for (int j = t; j < kSetSlots; j += kBlock) s_buf[j] = -1;
+    __syncthreads();
+    const int32_t A = s_off[nv];
+    for (int32_t cb = 0; cb < A; cb += kArcChunk) {
+      constexpr int U = kArcChunk / kBlock;
+      int32_t cu[U];
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        const int32_t j = cb + t + r * kBlock;
+        cu[r] = -1;
+        if (j < A) cu[r] = a.ac ? a.ac[a0 + j] : a.C[a.col[a0 + j]];
+      }
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        const int32_t j = cb + t + r * kBlock;
+        if (j >= A) continue;
+        int lo = 0, hi = nv - 1;  // tail: the last vertex whose row starts at or before j
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= j) lo = mid;
+          else hi = mid - 1;
+        }
+        const int32_t x = cu[r];
+        if (x == s_c[lo]) continue;
+        const int32_t key = (lo << 24) | x;
+        uint32_t h = ((uint32_t)key * 2654435761u) >> 21;  // 11 bits: kSetSlots
+        bool placed = false;
+        for (int q = 0; q < kSetProbe; ++q) {
+          int32_t cur = s_buf[h];
+          if (cur == -1) cur = atomicCAS(&s_buf[h], -1, key);
+          if (cur == -1) {  // first sighting of (lo, x)
+            const int slot = atomicAdd(&s_nc[lo], 1);
+            if (slot < kMaxCand) s_cand[slot * kBlock + lo] = x;
+            placed = true;
+            break;
+          }
+          if (cur == key) {
+            placed = true;
+            break;
+          }
+          h = (h + 1) & (kSetSlots - 1);
+        }
+        if (!placed) atomicAdd(&s_nc[lo], kMaxCand + 1);  // defer the vertex
+      }
+    }
+    __syncthreads();
+    const int nc = s_nc[t];
+    const bool over = nc > kMaxCand;
+    const bool is_b = t < nv && nc > 0 && !over;
+    if (t < nv) {
+      const int64_t v = v0 + t;
+      if (over) {
+        const int32_t slot = atomicAdd(&a.ctl->heavy_count, 1);
+        a.heavy[slot] = (int32_t)v;
+      } else if (nc == 0) {
+        a.prop[v] = kNone;
+      } else {
+        evals += nc;
+        boundary += 1;
+      }
+    }
+    int32_t npairs;
+    const int32_t ps = block_exclusive_scan(is_b ? 1 + nc : 0, &npairs);
+    if (is_b)
+      for (int j = 0; j <= nc; ++j) s_pv[ps + j] = (t << 4) | j;
+    __syncthreads();
+    // probes, software-pipelined: the label rows of the next batch are in
+    // flight while the current batch probes the tables
+    constexpr int kStride = (kBlock / kProbeLanes) * kProbeBatch;
+    auto pair_at = [&](int p, int32_t& x, int64_t& v) {
+      x = -1;
+      v = 0;
+      if (p < npairs) {
+        const int pv = s_pv[p], tv = pv >> 4, j = pv & 15;
+        v = v0 + tv;
+        x = j == 0 ? s_c[tv] : s_cand[(j - 1) * kBlock + tv];
+      }
+    };
+    if (kfits) {
+      int32_t xs[kProbeBatch], lab[kProbeBatch][kProbeRegs];
+      int64_t vs[kProbeBatch];
+      int p0 = g * kProbeBatch;
+#pragma unroll
+      for (int q = 0; q < kProbeBatch; ++q) {
+        pair_at(p0 + q, xs[q], vs[q]);
+#pragma unroll
+        for (int r = 0; r < kProbeRegs; ++r) {
+          const int i = lane + r * kProbeLanes;
+          lab[q][r] = (xs[q] >= 0 && i < k) ? a.Lvm[vs[q] * k + i] : 0;
+        }
+      }
+      for (; p0 < npairs; p0 += kStride) {
+        int32_t xn[kProbeBatch], labn[kProbeBatch][kProbeRegs];
+        int64_t vn[kProbeBatch];
+#pragma unroll
+        for (int q = 0; q < kProbeBatch; ++q) {
+          pair_at(p0 + kStride + q, xn[q], vn[q]);
+#pragma unroll
+          for (int r = 0; r < kProbeRegs; ++r) {
+            const int i = lane + r * kProbeLanes;
+            labn[q][r] = (xn[q] >= 0 && i < k) ? a.Lvm[vn[q] * k + i] : 0;
+          }
+        }
+        int32_t sums[kProbeBatch];
+#pragma unroll
+        for (int q = 0; q < kProbeBatch; ++q) {
+          int32_t sum = 0;
+#pragma unroll
+          for (int r = 0; r < kProbeRegs; ++r) {
+            const int i = lane + r * kProbeLanes;
+            if (xs[q] >= 0 && i < k) sum += a.t.N[cell(a.t, i, xs[q], lab[q][r])];
+          }
+          sums[q] = sum;
+        }
+#pragma unroll
+        for (int q = 0; q < kProbeBatch; ++q) {
+          const int32_t sq = group_sum<kProbeLanes>(sums[q]);
+          if (lane == 0 && xs[q] >= 0) s_buf[p0 + q] = sq;
+        }
+#pragma unroll
+        for (int q = 0; q < kProbeBatch; ++q) {
+          xs[q] = xn[q];
+          vs[q] = vn[q];
+#pragma unroll
+          for (int r = 0; r < kProbeRegs; ++r) lab[q][r] = labn[q][r];
+        }
+      }
+    } else {
+      for (int p0 = g * kProbeBatch; p0 < npairs; p0 += kStride) {
+#pragma unroll
+        for (int q = 0; q < kProbeBatch; ++q) {
+          int32_t x;
+          int64_t v;
+          pair_at(p0 + q, x, v);
+          int32_t sum = 0;
+          if (x >= 0) {
+            const int32_t* row = a.Lvm + v * k;
+            for (int i = lane; i < k; i += kProbeLanes) sum += a.t.N[cell(a.t, i, x, row[i])];
+          }
+          const int32_t sq = group_sum<kProbeLanes>(sum);
+          if (lane == 0 && x >= 0) s_buf[p0 + q] = sq;
+        }
+      }
+    }
+    __syncthreads();
+    if (is_b) {
+      const int64_t v = v0 + t;
+      const int32_t c = s_c[t];
+      const int64_t s_own = s_buf[ps];
+      const int64_t sc = a.s[c];
+      int64_t bestd = 0;
+      int32_t bestx = kNone;
+      for (int j = 0; j < nc; ++j) {
+        const int32_t x = s_cand[j * kBlock + t];
+        int64_t d = 2 * (s_own - (int64_t)s_buf[ps + 1 + j]) + (int64_t)k * ((int64_t)a.s[x] - sc - 1);
+        if (a.literal) d += k;
+        if (bestx == kNone || d < bestd || (d == bestd && x < bestx)) {
+          bestd = d;
+          bestx = x;
+        }
+      }
+      const bool p = bestd < 0;
+      a.prop[v] = p ? bestx : kNone;
+      if (p) {
+        a.dprop[v] = bestd;
+        ++nprop;
+      }
+    }
+    __syncthreads();
   }
   evals = wave_sum64(evals);
   nprop = wave_sum32(nprop);
@@ -260,6 +491,106 @@ __device__ inline int64_t move_counts(const PassArgs& a, int64_t v, int32_t from
   return acc;
 }
 
+// ---------------------------------------------------------------------------
+// Apply every proposal with per-workgroup aggregation.  Updates are keyed by
+// table cell (sizes use keys cells + cluster) and summed in an LDS hash
+// before one global atomic per distinct key; a key that finds no free slot
+// within kHashProbe steps goes straight to the global counter.  A net
+// update d on a counter whose previous value is `old` changes its square by
+// 2 old d + d^2, so the flush measures the objective change exactly.
+// ---------------------------------------------------------------------------
+constexpr int kHashSlots = 4096;
+constexpr int kHashProbe = 32;
+
+__device__ inline void agg_add(int32_t* hkey, int32_t* hval, const PassArgs& a, int64_t key,
+                               int32_t d, int64_t* dn2, int64_t* ds2) {
+  const int32_t k32 = (int32_t)key;
+  uint32_t h = ((uint32_t)k32 * 2654435761u) >> 20;  // 12 bits: kHashSlots
+#pragma unroll 1
+  for (int q = 0; q < kHashProbe; ++q) {
+    int32_t cur = hkey[h];
+    if (cur == -1) {
+      cur = atomicCAS(&hkey[h], -1, k32);
+      if (cur == -1) cur = k32;
+    }
+    if (cur == k32) {
+      atomicAdd(&hval[h], d);
+      return;
+    }
+    h = (h + 1) & (kHashSlots - 1);
+  }
+  if (key < a.cells) {
+    const int32_t old = atomicAdd(&a.t.N[key], d);
+    *dn2 += 2 * (int64_t)old * d + 1;
+  } else {
+    const int32_t old = atomicAdd(&a.s[key - a.cells], d);
+    *ds2 += 2 * (int64_t)old * d + 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  __shared__ int32_t hkey[kHashSlots];
+  __shared__ int32_t hval[kHashSlots];
+  for (int j = threadIdx.x; j < kHashSlots; j += kBlock) {
+    hkey[j] = -1;
+    hval[j] = 0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 64;
+  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) / 64;
+  int64_t dn2 = 0, ds2 = 0;
+  for (int64_t v0 = wave * 64; v0 < a.n; v0 += nwaves * 64) {
+    const int64_t v = v0 + lane;
+    const int32_t p = v < a.n ? a.prop[v] : kNone;
+    uint64_t mask = __ballot(p >= 0);
+    while (mask) {
+      const int b = __ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      const int64_t w = v0 + b;
+      const int32_t to = __shfl(p, b, 64);
+      const int32_t from = a.C[w];
+      const int32_t* row = a.Lvm + w * a.k;
+      for (int i = lane; i < a.k; i += 64) {
+        const int32_t l = row[i];
+        agg_add(hkey, hval, a, cell(a.t, i, to, l), +1, &dn2, &ds2);
+        agg_add(hkey, hval, a, cell(a.t, i, from, l), -1, &dn2, &ds2);
+      }
+      if (lane == 0) {
+        agg_add(hkey, hval, a, a.cells + to, +1, &dn2, &ds2);
+        agg_add(hkey, hval, a, a.cells + from, -1, &dn2, &ds2);
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < kHashSlots; j += kBlock) {
+    const int32_t key = hkey[j], d = hval[j];
+    if (key < 0 || d == 0) continue;
+    if (key < a.cells) {
+      const int32_t old = atomicAdd(&a.t.N[key], d);
+      dn2 += 2 * (int64_t)old * d + (int64_t)d * d;
+    } else {
+      const int32_t old = atomicAdd(&a.s[key - a.cells], d);
+      ds2 += 2 * (int64_t)old * d + (int64_t)d * d;
+    }
+  }
+  dn2 = wave_sum64(dn2);
+  ds2 = wave_sum64(ds2);
+  if (lane == 0) {
+    if (dn2) atomicAdd((unsigned long long*)&ctl->dN2, (unsigned long long)dn2);
+    if (ds2) atomicAdd((unsigned long long*)&ctl->dS2, (unsigned long long)ds2);
+  }
+}
+
+// Vertex w now sits in cluster c: every arc pointing at w learns it.
+__device__ inline void relabel_in_arcs(const PassArgs& a, int64_t w, int32_t c, int lane) {
+  if (!a.ac) return;
+  const int32_t b = a.in_ptr[w], e = a.in_ptr[w + 1];
+  for (int32_t p = b + lane; p < e; p += 64) a.ac[a.in_pos[p]] = c;
+}
+
 // The apply-type kernels walk the vertices 64 at a time per wave: one
 // coalesced load of the proposals, a ballot, then the wave serves each
 // selected vertex with its lanes spread over the partitions.
@@ -294,6 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(PassArgs a) {
       } else if (MODE == kCommitOrElect) {
         if (!fb) {
           if (lane == 0) a.C[w] = pw;
+          relabel_in_arcs(a, w, pw, lane);
         } else {
           move_counts(a, w, from, pw, -1, lane, &ds2);  // undo the batch
           if (lane == 0) {
@@ -318,6 +650,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(PassArgs a) {
           a.owner[to] = ~0ull;
           if (pw >= 0) a.C[w] = pw;
         }
+        if (pw >= 0) relabel_in_arcs(a, w, pw, lane);
       }
     }
   }
@@ -363,6 +696,7 @@ __global__ void k_end(Ctl* ctl) {
   ctl->nprop = 0;
   ctl->committed = 0;
   ctl->fallback = 0;
+  ctl->heavy_count = 0;
   ctl->dS2 = 0;
   ctl->dN2 = 0;
   if (ctl->passes >= ctl->max_rounds) ctl->done = 1;
@@ -380,20 +714,13 @@ __global__ void k_ctl_init(Ctl* ctl, const int64_t* acc, int32_t k, int32_t max_
 
 template <int G>
 void launch_score(const PassArgs& a, int grid, hipStream_t st) {
-  k_score<G><<<grid, kBlock, 0, st>>>(a);
+  k_score<G, false><<<grid, kBlock, 0, st>>>(a);
 }
 
 }  // namespace
 
-int score_lanes_auto(int32_t k) {
-  if (k <= 8) return 8;
-  if (k <= 24) return 16;
-  if (k <= 64) return 16;
-  return 32;
-}
-
 bool score_lanes_ok(int lanes) {
-  return lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32 || lanes == 64;
+  return lanes == 0 || lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32 || lanes == 64;
 }
 
 void launch_ctl_init(Ctl* ctl, const int64_t* acc, int32_t k, int32_t max_rounds,
@@ -405,6 +732,10 @@ void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, 
                   hipEvent_t score_begin, hipEvent_t score_end) {
   if (score_begin) (void)hipEventRecord(score_begin, st);
   switch (lanes) {
+    case 0:
+      k_score_tile<<<grid_score, kBlock, 0, st>>>(a);
+      k_score<64, true><<<256, kBlock, 0, st>>>(a);
+      break;
     case 4: launch_score<4>(a, grid_score, st); break;
     case 8: launch_score<8>(a, grid_score, st); break;
     case 16: launch_score<16>(a, grid_score, st); break;
@@ -413,7 +744,7 @@ void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, 
   }
   if (score_end) (void)hipEventRecord(score_end, st);
   k_begin<<<1, 1, 0, st>>>(a.ctl);
-  k_apply<kApplyAll><<<grid_apply, kBlock, 0, st>>>(a);
+  k_apply_all<<<grid_apply, kBlock, 0, st>>>(a);
   k_decide<<<1, 1, 0, st>>>(a.ctl);
   k_apply<kCommitOrElect><<<grid_apply, kBlock, 0, st>>>(a);
   k_apply<kFallbackCommit><<<grid_apply, kBlock, 0, st>>>(a);

@@ -23,29 +23,6 @@ inline int grid_for(int64_t items, int per_block, int cap = 65535) {
 __device__ inline int64_t gtid() { return (int64_t)blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ inline int64_t gstride() { return (int64_t)gridDim.x * blockDim.x; }
 
-// exclusive scan of one value per thread over a kBlock-thread workgroup
-__device__ int32_t block_exclusive_scan(int32_t x, int32_t* total) {
-  __shared__ int32_t wsum[kBlock / 64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int32_t v = x;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int32_t y = __shfl_up(v, o, 64);
-    if (lane >= o) v += y;
-  }
-  if (lane == 63) wsum[w] = v;
-  __syncthreads();
-  int32_t off = 0, tot = 0;
-#pragma unroll
-  for (int j = 0; j < kBlock / 64; ++j) {
-    if (j < w) off += wsum[j];
-    tot += wsum[j];
-  }
-  __syncthreads();
-  *total = tot;
-  return off + v - x;
-}
-
 template <typename T>
 __device__ T block_sum(T x) {
   __shared__ T part[kBlock / 64];
@@ -116,21 +93,31 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t* __restrict_
 __global__ __launch_bounds__(kBlock) void k_label_max(const int32_t* const* __restrict__ labels,
                                                       int64_t n, int32_t* __restrict__ maxlab,
                                                       int32_t* __restrict__ err) {
+  __shared__ int32_t s_m[kBlock / 64], s_lo[kBlock / 64];
   const int32_t* p = labels[blockIdx.y];
-  int32_t m = -1, bad = 0;
+  int32_t m = -1, lo = 0;
   for (int64_t v = gtid(); v < n; v += gstride()) {
-    int32_t x = p[v];
-    bad |= x < 0;
+    const int32_t x = p[v];
     m = max(m, x);
+    lo = min(lo, x);
   }
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     m = max(m, __shfl_xor(m, o, 64));
-    bad |= __shfl_xor(bad, o, 64);
+    lo = min(lo, __shfl_xor(lo, o, 64));
   }
   if ((threadIdx.x & 63) == 0) {
+    s_m[threadIdx.x >> 6] = m;
+    s_lo[threadIdx.x >> 6] = lo;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // one atomic per workgroup
+    for (int j = 1; j < kBlock / 64; ++j) {
+      m = max(m, s_m[j]);
+      lo = min(lo, s_lo[j]);
+    }
     atomicMax(&maxlab[blockIdx.y], m);
-    if (bad) atomicOr(err, kErrNegLabel);
+    if (lo < 0) atomicOr(err, kErrNegLabel);
   }
 }
 
@@ -139,7 +126,10 @@ __global__ __launch_bounds__(kBlock) void k_label_mark(const int32_t* const* __r
                                                        int32_t* __restrict__ flags) {
   const int32_t* p = labels[blockIdx.y];
   int32_t* f = flags + loff[blockIdx.y];
-  for (int64_t v = gtid(); v < n; v += gstride()) f[p[v]] = 1;
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    const int32_t x = p[v];
+    if (!f[x]) f[x] = 1;  // most labels repeat: skip the store when set
+  }
 }
 
 __global__ void k_label_counts(const int32_t* __restrict__ scan, const int64_t* __restrict__ loff,
@@ -428,6 +418,31 @@ __global__ __launch_bounds__(kBlock) void k_align_assign(const int32_t* __restri
   if (gtid() == 0) L2[i] = K0 + (rank[poff[i + 1]] - rank[b]);
 }
 
+// ---- in-arc lists and arc clusters -------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_in_degree(const int32_t* __restrict__ col, int64_t nnz,
+                                                      int32_t* __restrict__ indeg) {
+  for (int64_t j = gtid(); j < nnz; j += gstride()) atomicAdd(&indeg[col[j]], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_in_fill(const int32_t* __restrict__ col, int64_t nnz,
+                                                    int32_t* __restrict__ cursor,
+                                                    int32_t* __restrict__ in_pos) {
+  for (int64_t j = gtid(); j < nnz; j += gstride())
+    in_pos[atomicAdd(&cursor[col[j]], 1)] = (int32_t)j;
+}
+
+__global__ __launch_bounds__(kBlock) void k_arc_clusters(const int32_t* __restrict__ col,
+                                                         int64_t nnz,
+                                                         const int32_t* __restrict__ C,
+                                                         int32_t* __restrict__ ac) {
+  for (int64_t j = gtid(); j < nnz; j += gstride()) ac[j] = C[col[j]];
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_i32(const int32_t* __restrict__ src,
+                                                     int32_t* __restrict__ dst, int64_t n) {
+  for (int64_t j = gtid(); j < n; j += gstride()) dst[j] = src[j];
+}
+
 __global__ __launch_bounds__(kBlock) void k_dense_map(const int32_t* __restrict__ in, int64_t n,
                                                       const int32_t* __restrict__ scan,
                                                       int32_t* __restrict__ out) {
@@ -547,6 +562,24 @@ void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, con
   dim3 g(grid_for(maxL, kBlock, 64), k);
   k_hist_sumsq<<<g, kBlock, 0, st>>>(t, K0, acc + 1);
   k_sumsq<<<grid_for(total_entries, kBlock, 2048), kBlock, 0, st>>>(t.N, total_entries, acc + 2);
+}
+
+void launch_in_degree(const int32_t* col, int64_t nnz, int32_t* indeg, hipStream_t st) {
+  if (nnz > 0) k_in_degree<<<grid_for(nnz, kBlock, 4096), kBlock, 0, st>>>(col, nnz, indeg);
+}
+
+void launch_in_fill(const int32_t* col, int64_t nnz, int32_t* cursor, int32_t* in_pos,
+                    hipStream_t st) {
+  if (nnz > 0) k_in_fill<<<grid_for(nnz, kBlock, 4096), kBlock, 0, st>>>(col, nnz, cursor, in_pos);
+}
+
+void launch_arc_clusters(const int32_t* col, int64_t nnz, const int32_t* C, int32_t* ac,
+                         hipStream_t st) {
+  if (nnz > 0) k_arc_clusters<<<grid_for(nnz, kBlock, 4096), kBlock, 0, st>>>(col, nnz, C, ac);
+}
+
+void launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t st) {
+  if (n > 0) k_copy_i32<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(src, dst, n);
 }
 
 void launch_validate_csr(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
