@@ -30,7 +30,20 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_workload(name, n, device):
+def make_workload(name, n, device, cache=None):
+    import numpy as np
+    import synth
+    if cache and os.path.exists(cache):
+        z = np.load(cache)
+        return synth.Instance(name, z["row_ptr"], z["col"], z["labels"], z["init"], z["init"],
+                              {"cached": cache})
+    inst = _generate(name, n, device)
+    if cache:
+        np.savez(cache, row_ptr=inst.row_ptr, col=inst.col, labels=inst.labels, init=inst.init)
+    return inst
+
+
+def _generate(name, n, device):
     import synth
     if name == "gmm_knn":
         return synth.gmm_knn(n=n or 2_000_000, device=device, chunk=4096 if device != "cpu" else 0)
@@ -100,6 +113,9 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=50_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cache", default="", help="npz file to reuse the generated instance")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="run a 512 MiB elementwise copy first (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -114,7 +130,12 @@ def main():
     dev = "cuda"
     t0 = time.perf_counter()
     log(f"generating {args.workload}")
-    inst = make_workload(args.workload, args.n, dev)
+    if args.calibrate:
+        x = torch.ones(128 << 20, dtype=torch.int32, device=dev)
+        y = x + 0  # reads and writes 512 MiB once
+        torch.cuda.synchronize()
+        del x, y
+    inst = make_workload(args.workload, args.n, dev, args.cache or None)
     log(f"generated n={inst.n} nnz={inst.nnz} k={inst.k} in {time.perf_counter() - t0:.1f} s")
     D = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     rp, col, lab, ini = D(inst.row_ptr), D(inst.col), D(inst.labels), D(inst.init)

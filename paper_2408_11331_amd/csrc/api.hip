@@ -466,6 +466,13 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
     a.in_ptr = in_ptr;
     a.in_pos = in_pos;
     a.cells = S.total;
+    a.cn_bytes = S.K0 <= 256 ? 1 : (S.K0 <= 65536 ? 2 : 4);
+    if (a.cn_bytes == 4) {
+      a.Cn = S.C;
+    } else {
+      a.Cn = ar.get<uint8_t>(n * a.cn_bytes);
+      launch_narrow(S.C, a.Cn, a.cn_bytes, n, st);
+    }
     if (S.total + S.K0 >= ((int64_t)1 << 31)) throw Status{MCC_ENOTSUP};  // 32-bit update keys
 
     // the tiled scorer packs cluster ids in 24 bits

@@ -109,6 +109,7 @@ void launch_in_fill(const int32_t* col, int64_t nnz, int32_t* cursor, int32_t* i
 void launch_arc_clusters(const int32_t* col, int64_t nnz, const int32_t* C, int32_t* ac,
                          hipStream_t st);
 void launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t st);
+void launch_narrow(const int32_t* src, void* dst, int32_t bytes, int64_t n, hipStream_t st);
 void launch_validate_csr(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
                          int32_t* err, hipStream_t st);
 void launch_finish(const int32_t* C, const int32_t* rawid, int64_t n, int32_t* out,
@@ -144,7 +145,24 @@ struct PassArgs {
   const int32_t* in_ptr;
   const int32_t* in_pos;
   int64_t cells;      // table cells (keys >= cells address cluster sizes)
+  // Narrow copy of C (uint8 when K0 <= 256, uint16 when K0 <= 65536, else
+  // C itself) for the per-arc cluster gathers: a few MiB stay resident in
+  // every XCD's L2 where the int32 array would not.
+  void* Cn;
+  int32_t cn_bytes;
 };
+
+__device__ inline int32_t cn_load(const PassArgs& a, int64_t u) {
+  if (a.cn_bytes == 1) return ((const uint8_t*)a.Cn)[u];
+  if (a.cn_bytes == 2) return ((const uint16_t*)a.Cn)[u];
+  return ((const int32_t*)a.Cn)[u];
+}
+
+__device__ inline void cn_store(const PassArgs& a, int64_t u, int32_t c) {
+  if (a.cn_bytes == 1) ((uint8_t*)a.Cn)[u] = (uint8_t)c;
+  else if (a.cn_bytes == 2) ((uint16_t*)a.Cn)[u] = (uint16_t)c;
+  else ((int32_t*)a.Cn)[u] = c;
+}
 
 // Exclusive scan of one value per thread over a kBlock-thread workgroup;
 // *total receives the sum.  Contains barriers: call from all threads.

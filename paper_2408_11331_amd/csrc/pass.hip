@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
         x[r] = kInf;
         if (j < end) {
           // a self-loop points at v's own cluster and drops out with it
-          const int32_t cu = a.ac ? a.ac[j] : a.C[a.col[j]];
+          const int32_t cu = a.ac ? a.ac[j] : cn_load(a, a.col[j]);
           if (cu != cv) x[r] = cu;
         }
       }
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
         for (int r = 0; r < R; ++r) m = min(m, x[r]);
       } else {
         for (int64_t j = beg + lane; j < end; j += G) {
-          const int32_t cu = a.ac ? a.ac[j] : a.C[a.col[j]];
+          const int32_t cu = a.ac ? a.ac[j] : cn_load(a, a.col[j]);
           if (cu != cv && cu > last && cu < m) m = cu;
         }
       }
@@ -282,7 +282,7 @@ void k_score_tile(PassArgs a) {
       for (int r = 0; r < U; ++r) {
         const int32_t j = cb + t + r * kBlock;
         cu[r] = -1;
-        if (j < A) cu[r] = a.ac ? a.ac[a0 + j] : a.C[a.col[a0 + j]];
+        if (j < A) cu[r] = a.ac ? a.ac[a0 + j] : cn_load(a, a.col[a0 + j]);
       }
 #pragma unroll
       for (int r = 0; r < U; ++r) {
@@ -624,7 +624,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(PassArgs a) {
         dn2 += move_counts(a, w, from, pw, +1, lane, &ds2);
       } else if (MODE == kCommitOrElect) {
         if (!fb) {
-          if (lane == 0) a.C[w] = pw;
+          if (lane == 0) {
+            a.C[w] = pw;
+            cn_store(a, w, pw);
+          }
           relabel_in_arcs(a, w, pw, lane);
         } else {
           move_counts(a, w, from, pw, -1, lane, &ds2);  // undo the batch
@@ -648,7 +651,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(PassArgs a) {
         if (lane == 0) {
           a.owner[from] = ~0ull;
           a.owner[to] = ~0ull;
-          if (pw >= 0) a.C[w] = pw;
+          if (pw >= 0) {
+            a.C[w] = pw;
+            cn_store(a, w, pw);
+          }
         }
         if (pw >= 0) relabel_in_arcs(a, w, pw, lane);
       }

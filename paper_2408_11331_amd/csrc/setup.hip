@@ -443,6 +443,12 @@ __global__ __launch_bounds__(kBlock) void k_copy_i32(const int32_t* __restrict__
   for (int64_t j = gtid(); j < n; j += gstride()) dst[j] = src[j];
 }
 
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_narrow(const int32_t* __restrict__ src,
+                                                   T* __restrict__ dst, int64_t n) {
+  for (int64_t j = gtid(); j < n; j += gstride()) dst[j] = (T)src[j];
+}
+
 __global__ __launch_bounds__(kBlock) void k_dense_map(const int32_t* __restrict__ in, int64_t n,
                                                       const int32_t* __restrict__ scan,
                                                       int32_t* __restrict__ out) {
@@ -580,6 +586,14 @@ void launch_arc_clusters(const int32_t* col, int64_t nnz, const int32_t* C, int3
 
 void launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t st) {
   if (n > 0) k_copy_i32<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(src, dst, n);
+}
+
+void launch_narrow(const int32_t* src, void* dst, int32_t bytes, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  const int g = grid_for(n, kBlock, 2048);
+  if (bytes == 1) k_narrow<uint8_t><<<g, kBlock, 0, st>>>(src, (uint8_t*)dst, n);
+  else if (bytes == 2) k_narrow<uint16_t><<<g, kBlock, 0, st>>>(src, (uint16_t*)dst, n);
+  else k_narrow<int32_t><<<g, kBlock, 0, st>>>(src, (int32_t*)dst, n);
 }
 
 void launch_validate_csr(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
