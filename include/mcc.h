@@ -167,6 +167,48 @@ int mcc_mirkin(const int32_t* a, const int32_t* b, int64_t n, int64_t* result, v
 int mcc_canonicalize(const int32_t* in, int32_t* out, int64_t n, int32_t* clusters,
                      void* stream);
 
+/* One instance of a batch: the arguments of mcc_consensus.  `labels` is a
+ * HOST array of k device pointers. */
+typedef struct {
+  mcc_csr g;
+  const int32_t* const* labels;
+  int32_t k;
+  const int32_t* init;
+  int32_t* out;
+} mcc_problem;
+
+typedef struct {
+  void* stream;       /* hipStream_t or NULL */
+  int32_t max_rounds; /* per instance; 0 means 1000 */
+  uint32_t flags;     /* MCC_F_LITERAL honoured; others ignored */
+  int32_t lanes;      /* lanes per vertex in the batch scorer: 0 (= 16), 8, 16, 32 */
+  int32_t wg_per_cu;  /* resident workgroups per compute unit: 0 (= 2) .. 8 */
+  int32_t* status;    /* optional host int32[count]: per-instance return code */
+  int32_t solved_in_batch; /* out: instances the persistent kernel finished
+                              (the rest went through mcc_consensus) */
+  float ms_total;     /* out: wall time of the call on the stream */
+} mcc_batch_opts;
+
+/*
+ * Many independent consensus problems in one persistent launch (the groups
+ * of homogeneous partitions the paper solves independently, Methods, "The
+ * algorithm").  Each workgroup of the kernel takes one instance at a time
+ * from a queue ordered by estimated work (largest first) and runs the whole
+ * method of mcc_consensus on it; the launch is captured in a HIP graph.
+ * Instances beyond a workgroup's capacities (more than 256 partitions,
+ * label values far above n, large contingency tables) are solved by
+ * mcc_consensus on the same stream.  Every out[] and every stats field
+ * except the timings equals what mcc_consensus returns for the instance.
+ *
+ *  probs  host array of `count` problems.
+ *  stats  host array of `count` stats (outputs only) or NULL.
+ *  opts   may be NULL (defaults).
+ * Returns 0, or the first nonzero code of an instance (all instances are
+ * attempted; per-instance codes go to opts->status when given).
+ */
+int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stats,
+                        mcc_batch_opts* opts);
+
 /* Static text for a return code (for MCC_EDEVICE, the last HIP error seen
  * on this thread). */
 const char* mcc_strerror(int code);

@@ -18,7 +18,8 @@ MCC_F_VALIDATE, MCC_F_TRACE, MCC_F_LITERAL, MCC_F_PROFILE = 0x1, 0x2, 0x4, 0x8
 MCC_F_ARC_CACHE = 0x10
 
 # every function include/mcc.h declares
-EXPORTS = ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize", "mcc_strerror")
+EXPORTS = ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize",
+           "mcc_consensus_batch", "mcc_strerror")
 
 
 class Csr(ctypes.Structure):
@@ -48,6 +49,18 @@ class Stats(ctypes.Structure):
         return {f: getattr(self, f) for f in self.OUT}
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("g", Csr), ("labels", ctypes.c_void_p), ("k", ctypes.c_int32),
+                ("init", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p), ("max_rounds", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("lanes", ctypes.c_int32),
+                ("wg_per_cu", ctypes.c_int32), ("status", ctypes.c_void_p),
+                ("solved_in_batch", ctypes.c_int32), ("ms_total", ctypes.c_float)]
+
+
 class MccError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libmcc error {code}: {msg}")
@@ -69,6 +82,9 @@ def lib():
         L.mcc_objective.argtypes = [p, p, i32, i64, p, p]
         L.mcc_mirkin.argtypes = [p, p, i64, p, p]
         L.mcc_canonicalize.argtypes = [p, p, i64, p, p]
+        L.mcc_consensus_batch.argtypes = [ctypes.POINTER(Problem), i32, ctypes.POINTER(Stats),
+                                          ctypes.POINTER(BatchOpts)]
+        L.mcc_consensus_batch.restype = ctypes.c_int
         L.mcc_strerror.argtypes = [ctypes.c_int]
         L.mcc_strerror.restype = ctypes.c_char_p
         for f in ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize"):
@@ -172,3 +188,49 @@ def canonicalize(x, out=None, stream=None):
                                   out.data_ptr() if x.numel() else None, x.numel(),
                                   ctypes.byref(cl), _stream_ptr(stream)))
     return out, cl.value
+
+
+def consensus_batch(problems, *, max_rounds=0, flags=0, lanes=0, wg_per_cu=0, stream=None,
+                    outs=None):
+    """Solve many independent instances in one persistent launch.
+
+    problems: sequence of dicts with CUDA tensors ``row_ptr`` (int64),
+    ``col`` (int32), ``labels`` (int32 [k, n]) and optional ``init``.
+    Returns ``(outs, stats, status, info)``: output tensors, per-instance
+    stats dicts, per-instance return codes and the batch call's info
+    (instances finished in the persistent kernel, wall time)."""
+    import torch
+    count = len(problems)
+    keep = []
+    arr = (Problem * max(1, count))()
+    if outs is None:
+        outs = [torch.empty(p["row_ptr"].numel() - 1, dtype=torch.int32,
+                            device=p["row_ptr"].device) for p in problems]
+    for j, p in enumerate(problems):
+        rp = p["row_ptr"].contiguous()
+        col = _dev_i32(p["col"], "col")
+        rows, larr = _label_ptrs(p["labels"])
+        ini = p.get("init")
+        ini = None if ini is None else _dev_i32(ini, "init")
+        keep.extend([rp, col, rows, larr, ini])
+        n = rp.numel() - 1
+        arr[j].g = Csr(n, col.numel(), rp.data_ptr(), col.data_ptr() if col.numel() else None)
+        arr[j].labels = ctypes.cast(larr, ctypes.c_void_p)
+        arr[j].k = len(rows)
+        arr[j].init = ini.data_ptr() if ini is not None else None
+        arr[j].out = outs[j].data_ptr() if n > 0 else None
+    st = (Stats * max(1, count))()
+    status = (ctypes.c_int32 * max(1, count))()
+    o = BatchOpts()
+    o.stream = _stream_ptr(stream)
+    o.max_rounds = max_rounds
+    o.flags = flags
+    o.lanes = lanes
+    o.wg_per_cu = wg_per_cu
+    o.status = ctypes.cast(status, ctypes.c_void_p)
+    rc = lib().mcc_consensus_batch(arr, count, st, ctypes.byref(o))
+    codes = [status[j] for j in range(count)]
+    if rc not in (0, MCC_EINVAL):
+        _check(rc)
+    return outs, [st[j].as_dict() for j in range(count)], codes, \
+        {"solved_in_batch": o.solved_in_batch, "ms_total": o.ms_total, "rc": rc}

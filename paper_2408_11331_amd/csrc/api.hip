@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "impl.h"
 #include "mcc.h"
 
@@ -663,6 +664,188 @@ int mcc_canonicalize(const int32_t* in, int32_t* out, int64_t n, int32_t* cluste
   } catch (...) {
     return translate(std::current_exception());
   }
+}
+
+int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stats,
+                        mcc_batch_opts* opts) {
+  if (count < 0 || (count > 0 && !probs)) return MCC_EINVAL;
+  if (opts && opts->max_rounds < 0) return MCC_EINVAL;
+  const int32_t max_rounds = opts && opts->max_rounds > 0 ? opts->max_rounds : 1000;
+  const uint32_t flags = opts ? opts->flags : 0u;
+  int lanes = opts ? opts->lanes : 0;
+  if (!batch_lanes_ok(lanes)) return MCC_EINVAL;
+  if (lanes == 0) lanes = 16;
+  int wgpc = opts && opts->wg_per_cu > 0 ? opts->wg_per_cu : 2;
+  wgpc = std::min(wgpc, 8);
+  hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+  std::vector<int32_t> status(count, MCC_OK);
+  if (stats) memset(stats, 0, sizeof(mcc_stats) * (size_t)count);
+  if (opts) {
+    opts->solved_in_batch = 0;
+    opts->ms_total = 0.f;
+  }
+  if (count == 0) return MCC_OK;
+
+  // host-side argument checks, as mcc_consensus makes them
+  std::vector<int32_t> eligible;
+  std::vector<int32_t> fallback;
+  for (int32_t i = 0; i < count; ++i) {
+    const mcc_problem& p = probs[i];
+    const int64_t n = p.g.n;
+    bool ok = p.k >= 1 && n >= 0 && p.g.nnz >= 0 && p.labels &&
+              (int64_t)p.k * n < ((int64_t)1 << 31) && p.g.nnz < ((int64_t)1 << 31) - 1;
+    if (ok && n > 0)
+      ok = device_visible(p.g.row_ptr) && (p.g.nnz == 0 || device_visible(p.g.col)) &&
+           device_visible(p.out) && (!p.init || device_visible(p.init)) &&
+           labels_ok(p.labels, p.k);
+    if (!ok) {
+      status[i] = MCC_EINVAL;
+      continue;
+    }
+    if (p.k > 256) fallback.push_back(i);
+    else eligible.push_back(i);
+  }
+
+  int first_err = MCC_OK;
+  try {
+    Arena ar(st);
+    hipEvent_t e0, e1;
+    HIPCK(hipEventCreate(&e0));
+    HIPCK(hipEventCreate(&e1));
+    struct Ev2 {
+      hipEvent_t a, b;
+      ~Ev2() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } evg{e0, e1};
+    HIPCK(hipEventRecord(e0, st));
+    std::vector<BatchRes> hres(count);
+    if (!eligible.empty()) {
+      std::vector<const int32_t*> allptr;
+      std::vector<BatchInst> hinst(count);
+      std::vector<int64_t> loff(count, 0);
+      int64_t n_max = 1;
+      int32_t k_max = 1;
+      for (int32_t i : eligible) {
+        const mcc_problem& p = probs[i];
+        loff[i] = (int64_t)allptr.size();
+        for (int j = 0; j < p.k; ++j) allptr.push_back(p.labels[j]);
+        n_max = std::max<int64_t>(n_max, p.g.n);
+        k_max = std::max<int32_t>(k_max, p.k);
+      }
+      const int32_t** dptrs = ar.get<const int32_t*>((int64_t)allptr.size());
+      h2d(dptrs, ar.host(allptr), (int64_t)allptr.size(), st);
+      for (int32_t i : eligible) {
+        const mcc_problem& p = probs[i];
+        BatchInst b{};
+        b.n = p.g.n;
+        b.nnz = p.g.nnz;
+        b.row_ptr = p.g.row_ptr;
+        b.col = p.g.col;
+        b.labels = dptrs + loff[i];
+        b.init = p.init;
+        b.out = p.out;
+        b.k = p.k;
+        hinst[i] = b;
+      }
+      // largest estimated work first
+      std::vector<int32_t> order(eligible);
+      auto work = [&](int32_t i) { return probs[i].g.nnz + probs[i].g.n * (int64_t)probs[i].k; };
+      std::stable_sort(order.begin(), order.end(),
+                       [&](int32_t a, int32_t b) { return work(a) > work(b); });
+
+      BatchArgs ba{};
+      BatchWs& w = ba.ws;
+      w.n_max = n_max;
+      w.k_max = k_max;
+      w.flag_cap = 2 * n_max + 1024;
+      w.cells_cap = std::min<int64_t>(std::max<int64_t>(n_max * k_max, 1 << 18), 1 << 23);
+      const int64_t slots =
+          std::max<int64_t>(1, std::min<int64_t>((int64_t)eligible.size(), device_sms() * wgpc));
+      w.C = ar.get<int32_t>(slots * n_max);
+      w.rawid = ar.get<int32_t>(slots * n_max);
+      w.prop = ar.get<int32_t>(slots * n_max);
+      w.dprop = ar.get<int64_t>(slots * n_max);
+      w.s = ar.get<int32_t>(slots * n_max);
+      w.owner = ar.get<uint64_t>(slots * n_max);
+      w.Lvm = ar.get<int32_t>(slots * n_max * k_max);
+      w.N = ar.get<int32_t>(slots * w.cells_cap);
+      w.flags = ar.get<int32_t>(slots * w.flag_cap);
+      BatchInst* dinst = ar.get<BatchInst>(count);
+      h2d(dinst, ar.host(hinst), count, st);
+      int32_t* dorder = ar.get<int32_t>((int64_t)order.size());
+      h2d(dorder, ar.host(order), (int64_t)order.size(), st);
+      BatchRes* dres = ar.get<BatchRes>(count);
+      int32_t* dqueue = ar.get<int32_t>(1);
+      ba.inst = dinst;
+      ba.order = dorder;
+      ba.res = dres;
+      ba.queue = dqueue;
+      ba.count = (int32_t)order.size();
+      ba.max_rounds = max_rounds;
+      ba.literal = (flags & MCC_F_LITERAL) ? 1 : 0;
+      // the queue reset and the persistent kernel, as one captured graph
+      // (the legacy default stream cannot be captured: plain launches there)
+      if (st) {
+        sync(st);
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        launch_fill_i32(dqueue, 1, 0, st);
+        launch_batch(ba, lanes, (int)slots, st);
+        hipError_t ce = hipStreamEndCapture(st, &graph);
+        if (ce == hipSuccess) ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ce == hipSuccess) ce = hipGraphLaunch(exec, st);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        HIPCK(ce);
+      } else {
+        launch_fill_i32(dqueue, 1, 0, st);
+        launch_batch(ba, lanes, (int)slots, st);
+      }
+      d2h(hres.data(), dres, count, st);
+      sync(st);
+      for (int32_t i : eligible) {
+        if (hres[i].status == kBatchTooBig) fallback.push_back(i);
+        else if (hres[i].status == kBatchInvalid) status[i] = MCC_EINVAL;
+        else if (opts) opts->solved_in_batch += 1;
+      }
+      for (int32_t i : eligible) {
+        if (hres[i].status != 0 || !stats) continue;
+        mcc_stats& o = stats[i];
+        o.passes = hres[i].passes;
+        o.converged = hres[i].converged;
+        o.fallback_rounds = hres[i].fallback_rounds;
+        o.clusters = hres[i].clusters;
+        o.moves = hres[i].moves;
+        o.candidate_evals = hres[i].candidate_evals;
+        o.objective_init = hres[i].objective_init;
+        o.objective = hres[i].objective;
+      }
+    }
+    for (int32_t i : fallback) {
+      const mcc_problem& p = probs[i];
+      mcc_stats one;
+      memset(&one, 0, sizeof one);
+      one.max_rounds = max_rounds;
+      one.flags = flags & MCC_F_LITERAL;
+      one.stream = st;
+      const int rc = mcc_consensus(&p.g, p.labels, p.k, p.init, p.out, &one);
+      status[i] = rc;
+      if (stats && rc == MCC_OK) stats[i] = one;
+    }
+    HIPCK(hipEventRecord(e1, st));
+    sync(st);
+    if (opts) HIPCK(hipEventElapsedTime(&opts->ms_total, e0, e1));
+  } catch (...) {
+    return translate(std::current_exception());
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    if (status[i] != MCC_OK && first_err == MCC_OK) first_err = status[i];
+    if (opts && opts->status) opts->status[i] = status[i];
+  }
+  return first_err;
 }
 
 }  // extern "C"

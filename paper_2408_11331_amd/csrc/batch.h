@@ -1,0 +1,64 @@
+// Internal declarations of the batched persistent solver (batch.hip).
+#pragma once
+
+#include "impl.h"
+
+namespace mcc {
+
+// One instance of a batch (device copy).
+struct BatchInst {
+  int64_t n, nnz;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const int32_t* const* labels;  // device array of k device pointers
+  const int32_t* init;           // null: singletons
+  int32_t* out;
+  int32_t k;
+  int32_t pad;
+};
+
+// Per-instance result written by the kernel.
+struct BatchRes {
+  int32_t status;  // 0, kBatchTooBig (solve elsewhere) or kBatchInvalid
+  int32_t passes, converged, fallback_rounds, clusters;
+  int32_t pad;
+  int64_t moves, candidate_evals, objective_init, objective;
+};
+
+constexpr int32_t kBatchTooBig = 1;
+constexpr int32_t kBatchInvalid = 2;
+
+// Workspace: slot s of each array starts at base + s * (per-slot length).
+struct BatchWs {
+  int64_t n_max;      // vertices per slot
+  int32_t k_max;      // partitions per slot
+  int32_t pad;
+  int64_t cells_cap;  // table cells per slot
+  int64_t flag_cap;   // flag/scan entries per slot (label values, cluster ids)
+  int32_t* C;
+  int32_t* rawid;
+  int32_t* prop;
+  int64_t* dprop;
+  int32_t* s;
+  uint64_t* owner;
+  int32_t* Lvm;
+  int32_t* N;
+  int32_t* flags;
+};
+
+struct BatchArgs {
+  const BatchInst* inst;
+  const int32_t* order;  // queue order (largest work first)
+  BatchRes* res;
+  int32_t* queue;        // next queue position
+  int32_t count;
+  int32_t max_rounds;
+  int32_t literal;
+  int32_t pad;
+  BatchWs ws;
+};
+
+bool batch_lanes_ok(int lanes);
+void launch_batch(const BatchArgs& a, int lanes, int grid, hipStream_t st);
+
+}  // namespace mcc

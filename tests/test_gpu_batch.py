@@ -1,0 +1,113 @@
+"""Batched persistent solver: each instance's output equals the
+single-instance path (and the oracle) bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+KEYS = ("passes", "converged", "fallback_rounds", "clusters", "moves", "candidate_evals",
+        "objective_init", "objective")
+
+
+@pytest.fixture(scope="module")
+def mcc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2408_11331_amd as m
+    m.lib()
+    oracle.build(force=False)
+    return m
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def to_problem(inst, init="inst"):
+    ini = inst.init if isinstance(init, str) else init
+    return {"row_ptr": dev(inst.row_ptr), "col": dev(inst.col), "labels": dev(inst.labels),
+            "init": None if ini is None else dev(ini)}
+
+
+def instances():
+    out = []
+    specs = synth.sbm_batch_specs(count=24, n_range=(200, 3000), k_range=(2, 40))
+    for sp in specs:
+        out.append((synth.sbm_batch_instance(sp), "inst"))
+    for seed in range(12):
+        n = [1, 2, 50, 300, 700, 1500][seed % 6]
+        init = ["p0", "singleton", "random"][seed % 3]
+        inst = synth.random_instance(n, 1 + seed * 3, avg_deg=[2.0, 6.0, 30.0][seed % 3],
+                                     n_labels=[2, 5, 40][seed % 3], seed=100 + seed, init=init,
+                                     self_loops=seed % 4, dup_arcs=seed % 3)
+        out.append((inst, None if init == "singleton" else "inst"))
+    return out
+
+
+@pytest.mark.parametrize("lanes", [0, 8, 32])
+def test_batch_equals_single(mcc, lanes):
+    import torch
+    print(f"[gpu-case] batch lanes={lanes}", flush=True)
+    items = instances()
+    probs = [to_problem(i, init) for i, init in items]
+    outs, stats, codes, info = mcc.consensus_batch(probs, lanes=lanes)
+    torch.cuda.synchronize()
+    assert all(c == 0 for c in codes)
+    # singleton-initialised instances with large tables go to the
+    # single-instance path; the rest stay in the persistent kernel
+    assert info["solved_in_batch"] >= len(items) - 4
+    for (inst, init), out, st, p in zip(items, outs, stats, probs):
+        o2, st2 = mcc.consensus(p["row_ptr"], p["col"], p["labels"], p["init"])
+        assert np.array_equal(out.cpu().numpy(), o2.cpu().numpy())
+        for key in KEYS:
+            assert st[key] == st2[key], key
+    # and the oracle on a few
+    for (inst, init), out, st in list(zip(items, outs, stats))[::7]:
+        eo, est, _ = oracle.consensus(inst.row_ptr, inst.col, inst.labels,
+                                      None if init is None else inst.init)
+        assert np.array_equal(out.cpu().numpy(), eo)
+        for key in KEYS:
+            assert st[key] == est[key], key
+
+
+def test_batch_fallback_and_errors(mcc):
+    import torch
+    print("[gpu-case] batch fallback/errors", flush=True)
+    small = synth.random_instance(100, 3, 5.0, 4, seed=7)
+    huge = synth.random_instance(120, 3, 5.0, 4, seed=8)
+    huge.labels[1] = huge.labels[1] * 1_000_003 + 5  # label values far above n: not batchable
+    bad = synth.random_instance(90, 2, 5.0, 4, seed=9)
+    bad.labels[0, 3] = -1
+    many_k = synth.random_instance(40, 300, 4.0, 3, seed=10)  # k > 256
+    items = [small, huge, bad, many_k]
+    probs = [to_problem(i) for i in items]
+    outs, stats, codes, info = mcc.consensus_batch(probs, max_rounds=50)
+    torch.cuda.synchronize()
+    assert codes == [0, 0, mcc.MCC_EINVAL, 0]
+    assert info["solved_in_batch"] == 1 and info["rc"] == mcc.MCC_EINVAL
+    for j in (0, 1, 3):
+        inst = items[j]
+        eo, est, _ = oracle.consensus(inst.row_ptr, inst.col, inst.labels, inst.init,
+                                      max_rounds=50)
+        assert np.array_equal(outs[j].cpu().numpy(), eo)
+        for key in KEYS:
+            assert stats[j][key] == est[key], (j, key)
+
+
+def test_batch_max_rounds_and_literal(mcc):
+    import torch
+    print("[gpu-case] batch max_rounds/literal", flush=True)
+    items = [synth.random_instance(400, 5, 6.0, 5, seed=20 + j, init="singleton") for j in range(5)]
+    probs = [to_problem(i, None) for i in items]
+    for mr in (1, 2):
+        outs, stats, codes, _ = mcc.consensus_batch(probs, max_rounds=mr, flags=mcc.MCC_F_LITERAL)
+        torch.cuda.synchronize()
+        for inst, out, st in zip(items, outs, stats):
+            eo, est, _ = oracle.consensus(inst.row_ptr, inst.col, inst.labels, None,
+                                          max_rounds=mr, literal=True)
+            assert np.array_equal(out.cpu().numpy(), eo)
+            assert st["passes"] == est["passes"] and st["objective"] == est["objective"]
