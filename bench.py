@@ -54,6 +54,125 @@ def _generate(name, n, device):
     raise SystemExit(f"unknown workload {name}")
 
 
+def _batch_one(spec):
+    import synth
+    return synth.sbm_batch_instance(spec)
+
+
+def _lfr_one(args):
+    import synth
+    n, k, seed = args
+    return synth.lfr(n=n, k=k, w=4 + seed, mean_deg=16.0 if n > 50_000 else 20.0,
+                     max_deg=200, min_comm=50, max_comm=1000)
+
+
+def gen_parallel(fn, items, workers=16):
+    import multiprocessing as mp
+    if len(items) <= 2:
+        return [fn(x) for x in items]
+    with mp.get_context("fork").Pool(min(workers, len(items))) as pool:
+        return pool.map(fn, items, chunksize=max(1, len(items) // (workers * 4)))
+
+
+def bench_batch(args):
+    """Config sbm_batch: many SBM instances, one persistent launch, against
+    solving them one at a time."""
+    import numpy as np
+    import torch
+
+    import paper_2408_11331_amd as mcc
+    import synth
+    count = args.count or 4096
+    t0 = time.perf_counter()
+    specs = synth.sbm_batch_specs(count=count)
+    insts = gen_parallel(_batch_one, specs)
+    log(f"generated {count} instances in {time.perf_counter() - t0:.1f} s")
+    D = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    probs = [{"row_ptr": D(i.row_ptr), "col": D(i.col), "labels": D(i.labels), "init": D(i.init)}
+             for i in insts]
+    outs = [torch.empty(i.n, dtype=torch.int32, device="cuda") for i in insts]
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        mcc.consensus_batch(probs, outs=outs, wg_per_cu=args.wg_per_cu, lanes=args.lanes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, stats, codes, info = mcc.consensus_batch(probs, outs=outs, wg_per_cu=args.wg_per_cu,
+                                                    lanes=args.lanes)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    assert all(c == 0 for c in codes)
+    batch_out = [o.cpu().numpy() for o in outs]
+    # one at a time, same instances, once
+    t0 = time.perf_counter()
+    same = True
+    for j, p in enumerate(probs):
+        o, st = mcc.consensus(p["row_ptr"], p["col"], p["labels"], p["init"])
+        same &= bool(np.array_equal(o.cpu().numpy(), batch_out[j])) and \
+            st["objective"] == stats[j]["objective"]
+    torch.cuda.synchronize()
+    el1 = time.perf_counter() - t0
+    evals = sum(st["candidate_evals"] for st in stats)
+    return {
+        "metric": "batched solves/s", "value": count / el, "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "sbm_batch", "instances": count,
+                   "sum_n": int(sum(i.n for i in insts)), "sum_nnz": int(sum(i.nnz for i in insts)),
+                   "sum_nk": int(sum(i.n * i.k for i in insts)),
+                   "solved_in_persistent_kernel": info["solved_in_batch"],
+                   "candidate_evals": int(evals), "wg_per_cu": args.wg_per_cu,
+                   "lanes": args.lanes},
+        "one_at_a_time": {"solves_per_s": count / el1, "seconds": el1,
+                          "identical_outputs": bool(same)},
+        "speedup_vs_one_at_a_time": el1 / el,
+    }
+
+
+def bench_served(args):
+    """Config served: Poisson request stream (80% small LFR-style, 20%
+    large), rate swept; continuous batching against one solve at a time."""
+    from paper_2408_11331_amd import serve
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(20240825))
+    small = [(int(np.exp(rng.uniform(np.log(1000), np.log(50_000)))), int(rng.integers(4, 17)), j)
+             for j in range(16)]
+    large = [(n, 32, 100 + j) for j, n in enumerate(args.large_sizes)]
+    t0 = time.perf_counter()
+    insts = gen_parallel(_lfr_one, small + large)
+    log(f"generated request pool ({len(insts)}) in {time.perf_counter() - t0:.1f} s")
+    pool = []
+    for i in insts:
+        pool.append(serve.Request(i.row_ptr, i.col, i.labels, i.init))
+    # 80% small / 20% large by replicating pool entries
+    weighted = [p for p in pool[:len(small)]] * 4 + [p for p in pool[len(small):]] * \
+        max(1, (4 * len(small)) // (4 * max(1, len(large))))
+    rates = [float(r) for r in args.rates.split(",")]
+    sweep = []
+    for rate in rates:
+        reqs, summ = serve.run_served(weighted, rate=rate, count=args.requests, seed=11,
+                                      budget_bytes=args.budget_gib << 30)
+        base_reqs, base = serve.run_one_at_a_time(weighted, rate=rate, count=args.requests,
+                                                  seed=11)
+        same = all(np.array_equal(a.out, b.out) for a, b in zip(reqs, base_reqs))
+        sweep.append({"rate_per_s": rate, "served": summ, "one_at_a_time": base,
+                      "identical_outputs": bool(same)})
+        log(f"rate {rate}: served {summ['solves_per_s']:.1f}/s p99 {summ['p99_ms']:.1f} ms; "
+            f"plain {base['solves_per_s']:.1f}/s p99 {base['p99_ms']:.1f} ms")
+    best = max(sweep, key=lambda x: x["served"]["solves_per_s"])
+    return {
+        "metric": "served solves/s", "value": best["served"]["solves_per_s"], "unit": "solves/s",
+        "n_gpus": 1, "steps": len(rates), "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "served", "requests_per_rate": args.requests,
+                   "pool": [[i.n, i.k, i.nnz] for i in insts], "budget_gib": args.budget_gib},
+        "p50_ms": best["served"]["p50_ms"], "p99_ms": best["served"]["p99_ms"],
+        "sweep": sweep,
+    }
+
+
 def score_bytes(inst, passes, boundary, accepted):
     """Algorithmic HBM bytes of all scoring launches of one solve: per pass
     the CSR (row_ptr, col), the consensus array and the proposal array once,
@@ -108,7 +227,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="gmm_knn", choices=["gmm_knn", "lfr", "sbm_small"])
+    ap.add_argument("--workload", default="gmm_knn",
+                    choices=["gmm_knn", "lfr", "sbm_small", "sbm_batch", "served"])
+    ap.add_argument("--count", type=int, default=0, help="sbm_batch: instances")
+    ap.add_argument("--wg-per-cu", type=int, default=0, help="sbm_batch: resident workgroups")
+    ap.add_argument("--rates", default="20,80,320", help="served: arrival rates per second")
+    ap.add_argument("--requests", type=int, default=120, help="served: requests per rate")
+    ap.add_argument("--large-sizes", type=lambda s: [int(x) for x in s.split(",")],
+                    default=[200_000, 500_000, 1_000_000], help="served: large request sizes")
+    ap.add_argument("--budget-gib", type=int, default=64, help="served: HBM admission budget")
     ap.add_argument("--n", type=int, default=0, help="override the vertex count")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=50_000)
@@ -127,6 +254,10 @@ def main():
 
     import paper_2408_11331_amd as mcc
     mcc.lib()
+    if args.workload in ("sbm_batch", "served"):
+        rec = bench_batch(args) if args.workload == "sbm_batch" else bench_served(args)
+        print(json.dumps(rec), flush=True)
+        return
     dev = "cuda"
     t0 = time.perf_counter()
     log(f"generating {args.workload}")
