@@ -1,12 +1,13 @@
 """Consensus-solve serving with continuous batching on one GPU.
 
 Requests (a graph, k partitions, an optional initial consensus) arrive at
-any time.  Small requests are solved in batches by the persistent batched
-kernel (``mcc_consensus_batch``); large ones by the multi-workgroup
+any time.  Small requests (a few thousand vertices, where one workgroup per
+instance is the right size) are solved in batches by the persistent
+batched kernel (``mcc_consensus_batch``); larger ones by the multi-workgroup
 single-instance path (``mcc_consensus``).  Several workers, each with its
-own HIP stream, pull from one admission queue: while one batch is on the
-device the next one is admitted and launched on another stream, so work
-from requests that arrived at different times overlaps on the GPU.
+own HIP stream, pull from one admission queue: while one batch or solve is
+on the device the next one is admitted and launched on another stream, so
+work from requests that arrived at different times overlaps on the GPU.
 Admission is bounded by an HBM budget: a request is taken only when its
 device footprint fits next to everything in flight.
 
@@ -122,8 +123,8 @@ class GpuBackend:
 class Server:
     """Admission queue plus worker threads that own one stream each."""
 
-    def __init__(self, budget_bytes: int = 16 << 30, large_n: int = 50_000,
-                 max_batch: int = 256, small_workers: int = 2, large_workers: int = 1,
+    def __init__(self, budget_bytes: int = 16 << 30, large_n: int = 8192,
+                 max_batch: int = 256, small_workers: int = 2, large_workers: int = 3,
                  max_rounds: int = 0, backend=None):
         self.backend = backend if backend is not None else GpuBackend(max_rounds)
         self.budget = int(budget_bytes)
