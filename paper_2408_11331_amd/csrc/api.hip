@@ -274,15 +274,20 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
     sumL += Lh[i];
   }
   // Blocked tables with dense label ids: the final tables when the labels
-  // are not aligned, the source of the alignment otherwise.
+  // are not aligned; otherwise first built from a sample of the vertices as
+  // the source of the alignment (any injective relabelling is exact, so the
+  // sample only steers the layout).
   int64_t total = 0;
   Tables bt = blocked_tables(ar, *S, S->lab.L, Lh, st, &total);
-  launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, bt, st);
+  const bool try_align = want_rows && K0 <= kAlignMaxClusters;
+  const int64_t stride = try_align ? std::max<int64_t>(1, n / (1 << 18)) : 1;
+  launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, bt, st, stride);
   S->t = bt;
   S->maxL = maxL;
   S->total = total;
+  bool aligned = false;
 
-  if (want_rows && K0 <= kAlignMaxClusters) {
+  if (try_align) {
     std::vector<int64_t> poff(k + 1, 0);
     for (int i = 0; i < k; ++i) poff[i + 1] = poff[i] + Lh[i];
     int64_t* dpoff = ar.get<int64_t>(k + 1);
@@ -317,7 +322,12 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
       S->t = it;
       S->maxL = Lmax;
       S->total = cells;
+      aligned = true;
     }
+  }
+  if (try_align && !aligned && stride > 1) {  // sampled blocked tables: count them all
+    launch_fill_i32(bt.N, total, 0, st);
+    launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, bt, st, 1);
   }
   if (want_rows) {
     S->Lvm = ar.get<int32_t>(n * k);

@@ -93,9 +93,10 @@ void launch_cluster_assign(const int32_t* init, int64_t n, const int32_t* cmap, 
 void launch_iota(int32_t* a, int64_t n, hipStream_t st);
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st);
 void launch_fill_u64(uint64_t* a, int64_t n, uint64_t v, hipStream_t st);
+// Counts every stride-th vertex (stride 1: the exact tables).
 void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t* loff,
                   const int32_t* fmap, int64_t n, int32_t k, int32_t K0, Tables t,
-                  hipStream_t st);
+                  hipStream_t st, int64_t stride = 1);
 void launch_sizes(const int32_t* C, int64_t n, int32_t K0, int32_t* s, hipStream_t st);
 void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, const int32_t* s,
                        int64_t total_entries,

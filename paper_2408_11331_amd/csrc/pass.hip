@@ -740,7 +740,8 @@ void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, 
   switch (lanes) {
     case 0:
       k_score_tile<<<grid_score, kBlock, 0, st>>>(a);
-      k_score<64, true><<<256, kBlock, 0, st>>>(a);
+      // deferred vertices: one per wave, as many waves as the chip holds
+      k_score<64, true><<<grid_score, kBlock, 0, st>>>(a);
       break;
     case 4: launch_score<4>(a, grid_score, st); break;
     case 8: launch_score<8>(a, grid_score, st); break;

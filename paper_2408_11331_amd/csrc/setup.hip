@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
                                                   const int32_t* const* __restrict__ labels,
                                                   const int64_t* __restrict__ loff,
                                                   const int32_t* __restrict__ fmap, int64_t n,
-                                                  int32_t K0, Tables t) {
+                                                  int32_t K0, Tables t, int64_t stride) {
   __shared__ int32_t h[kLdsHist];
   const int i = blockIdx.y;
   const int32_t Li = t.L[i];
@@ -241,13 +241,16 @@ __global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
     for (int j = threadIdx.x; j < entries; j += kBlock) h[j] = 0;
     __syncthreads();
   }
-  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t v0 = (int64_t)blockIdx.x * per;
-  const int64_t v1 = min(n, v0 + per);
-  // partition-major input labels (coalesced) mapped to their ids
+  // every stride-th vertex (stride 1: all of them)
+  const int64_t ns = (n + stride - 1) / stride;
+  const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
+  const int64_t j0 = (int64_t)blockIdx.x * per;
+  const int64_t j1 = min(ns, j0 + per);
+  // partition-major input labels (coalesced when stride is 1) mapped to their ids
   const int32_t* p = labels[i];
   const int32_t* map = fmap + loff[i];
-  for (int64_t v = v0 + threadIdx.x; v < v1; v += kBlock) {
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kBlock) {
+    const int64_t v = j * stride;
     const int32_t x = C[v], l = map[p[v]];
     if (lds) atomicAdd(&h[x * Li + l], 1);
     else atomicAdd(&t.N[cell(t, i, x, l)], 1);
@@ -546,14 +549,14 @@ void launch_fill_u64(uint64_t* a, int64_t n, uint64_t v, hipStream_t st) {
 
 void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t* loff,
                   const int32_t* fmap, int64_t n, int32_t k, int32_t K0, Tables t,
-                  hipStream_t st) {
+                  hipStream_t st, int64_t stride) {
   // enough workgroups per partition to fill the chip, few enough that the
   // LDS flush stays small next to the counting
-  int64_t per_part = (n + 4095) / 4096;
+  int64_t per_part = ((n + stride - 1) / stride + 4095) / 4096;
   if (per_part > 64) per_part = 64;
   if (per_part < 1) per_part = 1;
   dim3 g((unsigned)per_part, k);
-  k_build<<<g, kBlock, 0, st>>>(C, dlabels, loff, fmap, n, K0, t);
+  k_build<<<g, kBlock, 0, st>>>(C, dlabels, loff, fmap, n, K0, t, stride);
 }
 
 void launch_sizes(const int32_t* C, int64_t n, int32_t K0, int32_t* s, hipStream_t st) {
