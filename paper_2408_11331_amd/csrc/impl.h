@@ -57,9 +57,12 @@ struct Tables {
   int32_t interleaved;
 };
 
-__host__ __device__ inline int64_t cell(const Tables& t, int i, int32_t x, int32_t l) {
-  return t.interleaved ? ((int64_t)x * t.Lmax + l) * t.k + i
-                       : t.toff[i] + (int64_t)x * t.L[i] + l;
+// Table cell of (partition i, cluster x, label id l).  Every table holds
+// fewer than 2^31 cells (checked when it is sized), so the index is
+// computed in 32 bits.
+__device__ inline uint32_t cell(const Tables& t, int i, int32_t x, int32_t l) {
+  return t.interleaved ? ((uint32_t)x * (uint32_t)t.Lmax + (uint32_t)l) * (uint32_t)t.k + i
+                       : (uint32_t)t.toff[i] + (uint32_t)x * (uint32_t)t.L[i] + (uint32_t)l;
 }
 
 // ---- setup kernels (setup.hip) -------------------------------------------

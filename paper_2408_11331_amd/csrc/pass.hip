@@ -275,25 +275,33 @@ void k_score_tile(PassArgs a) {
     for (int j = t; j < kSetSlots; j += kBlock) s_buf[j] = -1;
     __syncthreads();
     const int32_t A = s_off[nv];
+    // each thread takes U consecutive arcs of every chunk: one search for
+    // the tail of the first, then a walk along the row offsets
+    const int32_t* colp = a.col + a0;
     for (int32_t cb = 0; cb < A; cb += kArcChunk) {
       constexpr int U = kArcChunk / kBlock;
+      const int32_t jt = cb + t * U;
       int32_t cu[U];
 #pragma unroll
       for (int r = 0; r < U; ++r) {
-        const int32_t j = cb + t + r * kBlock;
+        const int32_t j = jt + r;
         cu[r] = -1;
-        if (j < A) cu[r] = a.ac ? a.ac[a0 + j] : cn_load(a, a.col[a0 + j]);
+        if (j < A) cu[r] = a.ac ? a.ac[a0 + j] : cn_load(a, colp[j]);
+      }
+      int lo = 0;
+      if (jt < A) {
+        int hi = nv - 1;  // tail: the last vertex whose row starts at or before jt
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= jt) lo = mid;
+          else hi = mid - 1;
+        }
       }
 #pragma unroll
       for (int r = 0; r < U; ++r) {
-        const int32_t j = cb + t + r * kBlock;
+        const int32_t j = jt + r;
         if (j >= A) continue;
-        int lo = 0, hi = nv - 1;  // tail: the last vertex whose row starts at or before j
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_off[mid] <= j) lo = mid;
-          else hi = mid - 1;
-        }
+        while (s_off[lo + 1] <= j) ++lo;
         const int32_t x = cu[r];
         if (x == s_c[lo]) continue;
         const int32_t key = (lo << 24) | x;
@@ -341,18 +349,18 @@ void k_score_tile(PassArgs a) {
     // probes, software-pipelined: the label rows of the next batch are in
     // flight while the current batch probes the tables
     constexpr int kStride = (kBlock / kProbeLanes) * kProbeBatch;
-    auto pair_at = [&](int p, int32_t& x, int64_t& v) {
+    auto pair_at = [&](int p, int32_t& x, uint32_t& row) {
       x = -1;
-      v = 0;
+      row = 0;
       if (p < npairs) {
         const int pv = s_pv[p], tv = pv >> 4, j = pv & 15;
-        v = v0 + tv;
+        row = (uint32_t)(v0 + tv) * (uint32_t)k;
         x = j == 0 ? s_c[tv] : s_cand[(j - 1) * kBlock + tv];
       }
     };
     if (kfits) {
       int32_t xs[kProbeBatch], lab[kProbeBatch][kProbeRegs];
-      int64_t vs[kProbeBatch];
+      uint32_t vs[kProbeBatch];  // row offsets v * k (n * k < 2^31)
       int p0 = g * kProbeBatch;
 #pragma unroll
       for (int q = 0; q < kProbeBatch; ++q) {
@@ -360,19 +368,19 @@ void k_score_tile(PassArgs a) {
 #pragma unroll
         for (int r = 0; r < kProbeRegs; ++r) {
           const int i = lane + r * kProbeLanes;
-          lab[q][r] = (xs[q] >= 0 && i < k) ? a.Lvm[vs[q] * k + i] : 0;
+          lab[q][r] = (xs[q] >= 0 && i < k) ? a.Lvm[vs[q] + i] : 0;
         }
       }
       for (; p0 < npairs; p0 += kStride) {
         int32_t xn[kProbeBatch], labn[kProbeBatch][kProbeRegs];
-        int64_t vn[kProbeBatch];
+        uint32_t vn[kProbeBatch];
 #pragma unroll
         for (int q = 0; q < kProbeBatch; ++q) {
           pair_at(p0 + kStride + q, xn[q], vn[q]);
 #pragma unroll
           for (int r = 0; r < kProbeRegs; ++r) {
             const int i = lane + r * kProbeLanes;
-            labn[q][r] = (xn[q] >= 0 && i < k) ? a.Lvm[vn[q] * k + i] : 0;
+            labn[q][r] = (xn[q] >= 0 && i < k) ? a.Lvm[vn[q] + i] : 0;
           }
         }
         int32_t sums[kProbeBatch];
@@ -404,11 +412,11 @@ void k_score_tile(PassArgs a) {
 #pragma unroll
         for (int q = 0; q < kProbeBatch; ++q) {
           int32_t x;
-          int64_t v;
-          pair_at(p0 + q, x, v);
+          uint32_t ro;
+          pair_at(p0 + q, x, ro);
           int32_t sum = 0;
           if (x >= 0) {
-            const int32_t* row = a.Lvm + v * k;
+            const int32_t* row = a.Lvm + ro;
             for (int i = lane; i < k; i += kProbeLanes) sum += a.t.N[cell(a.t, i, x, row[i])];
           }
           const int32_t sq = group_sum<kProbeLanes>(sum);
