@@ -156,6 +156,22 @@ struct PassArgs {
   int32_t cn_bytes;
 };
 
+// Compile-time variants: CN is the narrow copy's width in bytes (0: read the
+// per-arc cache), IL selects the interleaved table layout.
+template <int CN>
+__device__ inline int32_t cn_load_t(const PassArgs& a, int64_t j, int32_t u) {
+  if (CN == 0) return a.ac[j];
+  if (CN == 1) return ((const uint8_t*)a.Cn)[u];
+  if (CN == 2) return ((const uint16_t*)a.Cn)[u];
+  return ((const int32_t*)a.Cn)[u];
+}
+
+template <bool IL>
+__device__ inline uint32_t cell_t(const Tables& t, int i, int32_t x, int32_t l) {
+  if (IL) return ((uint32_t)x * (uint32_t)t.Lmax + (uint32_t)l) * (uint32_t)t.k + i;
+  return (uint32_t)t.toff[i] + (uint32_t)x * (uint32_t)t.L[i] + (uint32_t)l;
+}
+
 __device__ inline int32_t cn_load(const PassArgs& a, int64_t u) {
   if (a.cn_bytes == 1) return ((const uint8_t*)a.Cn)[u];
   if (a.cn_bytes == 2) return ((const uint16_t*)a.Cn)[u];

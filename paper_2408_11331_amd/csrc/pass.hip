@@ -249,6 +249,7 @@ constexpr int kProbeLanes = 16;
 constexpr int kProbeRegs = 64 / kProbeLanes;  // labels per lane when k <= 64
 constexpr int kProbeBatch = 4;
 
+template <int CN, bool IL>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_score_tile(PassArgs a) {
   if (a.ctl->done) return;
@@ -286,7 +287,7 @@ void k_score_tile(PassArgs a) {
       for (int r = 0; r < U; ++r) {
         const int32_t j = jt + r;
         cu[r] = -1;
-        if (j < A) cu[r] = a.ac ? a.ac[a0 + j] : cn_load(a, colp[j]);
+        if (j < A) cu[r] = cn_load_t<CN>(a, a0 + j, CN ? colp[j] : 0);
       }
       int lo = 0;
       if (jt < A) {
@@ -390,7 +391,7 @@ void k_score_tile(PassArgs a) {
 #pragma unroll
           for (int r = 0; r < kProbeRegs; ++r) {
             const int i = lane + r * kProbeLanes;
-            if (xs[q] >= 0 && i < k) sum += a.t.N[cell(a.t, i, xs[q], lab[q][r])];
+            if (xs[q] >= 0 && i < k) sum += a.t.N[cell_t<IL>(a.t, i, xs[q], lab[q][r])];
           }
           sums[q] = sum;
         }
@@ -417,7 +418,7 @@ void k_score_tile(PassArgs a) {
           int32_t sum = 0;
           if (x >= 0) {
             const int32_t* row = a.Lvm + ro;
-            for (int i = lane; i < k; i += kProbeLanes) sum += a.t.N[cell(a.t, i, x, row[i])];
+            for (int i = lane; i < k; i += kProbeLanes) sum += a.t.N[cell_t<IL>(a.t, i, x, row[i])];
           }
           const int32_t sq = group_sum<kProbeLanes>(sum);
           if (lane == 0 && x >= 0) s_buf[p0 + q] = sq;
@@ -747,7 +748,19 @@ void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, 
   if (score_begin) (void)hipEventRecord(score_begin, st);
   switch (lanes) {
     case 0:
-      k_score_tile<<<grid_score, kBlock, 0, st>>>(a);
+      if (a.ac) {
+        if (a.t.interleaved) k_score_tile<0, true><<<grid_score, kBlock, 0, st>>>(a);
+        else k_score_tile<0, false><<<grid_score, kBlock, 0, st>>>(a);
+      } else if (a.cn_bytes == 1) {
+        if (a.t.interleaved) k_score_tile<1, true><<<grid_score, kBlock, 0, st>>>(a);
+        else k_score_tile<1, false><<<grid_score, kBlock, 0, st>>>(a);
+      } else if (a.cn_bytes == 2) {
+        if (a.t.interleaved) k_score_tile<2, true><<<grid_score, kBlock, 0, st>>>(a);
+        else k_score_tile<2, false><<<grid_score, kBlock, 0, st>>>(a);
+      } else {
+        if (a.t.interleaved) k_score_tile<4, true><<<grid_score, kBlock, 0, st>>>(a);
+        else k_score_tile<4, false><<<grid_score, kBlock, 0, st>>>(a);
+      }
       // deferred vertices: one per wave, as many waves as the chip holds
       k_score<64, true><<<grid_score, kBlock, 0, st>>>(a);
       break;

@@ -109,6 +109,8 @@ def test_random_instances(mcc, seed, n, k, init):
     o = run_oracle(inst, ini)
     for lanes in (0, [4, 8, 16, 32, 64][seed % 5]):
         assert_same(run_gpu(mcc, inst, ini, lanes=lanes), o)
+    # neighbour clusters from the per-arc cache instead of gathers
+    assert_same(run_gpu(mcc, inst, ini, flags=mcc.MCC_F_ARC_CACHE), o)
 
 
 @pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
@@ -124,6 +126,23 @@ def test_high_degree_and_many_candidates(mcc, lanes):
     init = r.integers(0, 600, size=n).astype(np.int32)
     inst = synth.Instance("hub", rp, col, labels, init, init, {})
     assert_same(run_gpu(mcc, inst, lanes=lanes), run_oracle(inst))
+
+
+def test_many_clusters_blocked_tables(mcc):
+    # singleton start on 70 000 vertices: more clusters than the narrow
+    # cluster copies and the label alignment handle (full-width gathers,
+    # blocked table layout); 140 passes, 3 of them fallbacks
+    announce("many clusters")
+    inst = synth.random_instance(70_000, 3, avg_deg=4.0, n_labels=3, seed=61, init="singleton")
+    o = run_oracle(inst, None)
+    for flags in (0, mcc.MCC_F_ARC_CACHE):
+        assert_same(run_gpu(mcc, inst, None, flags=flags), o)
+
+
+def test_arc_cache_workloads(mcc):
+    announce("arc cache sbm_small/gmm_knn")
+    for inst in (synth.sbm_small(), synth.gmm_knn(n=5000)):
+        assert_same(run_gpu(mcc, inst, flags=mcc.MCC_F_ARC_CACHE), run_oracle(inst))
 
 
 def test_literal_self_term_ablation(mcc):
