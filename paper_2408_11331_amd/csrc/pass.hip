@@ -298,6 +298,7 @@ void k_score_tile(PassArgs a) {
           else hi = mid - 1;
         }
       }
+      int32_t prev = -1;  // the last key this thread placed: repeats skip the set
 #pragma unroll
       for (int r = 0; r < U; ++r) {
         const int32_t j = jt + r;
@@ -306,6 +307,8 @@ void k_score_tile(PassArgs a) {
         const int32_t x = cu[r];
         if (x == s_c[lo]) continue;
         const int32_t key = (lo << 24) | x;
+        if (key == prev) continue;
+        prev = key;
         uint32_t h = ((uint32_t)key * 2654435761u) >> 21;  // 11 bits: kSetSlots
         bool placed = false;
         for (int q = 0; q < kSetProbe; ++q) {
