@@ -226,25 +226,25 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
 // ---------------------------------------------------------------------------
 // Tiled scorer.  A workgroup owns a tile of kBlock consecutive vertices:
 //  1. the tile's row offsets and clusters go to LDS;
-//  2. its arcs are walked in chunks, every thread taking kArcChunk / kBlock
-//     arcs with independent loads; each arc whose head lies in another
-//     cluster inserts the key (tail, head cluster) into a tile-wide LDS hash
-//     set, and the first insertion of a key appends the cluster to the
-//     tail's candidate list (a self-loop points at the own cluster and drops
-//     out with it);
-//  3. the (vertex, cluster) pairs of the tile's boundary vertices, own
-//     cluster first, form a flat list that groups of kProbeLanes lanes probe
-//     four pairs at a time, lanes spread over the partitions;
-//  4. one thread per vertex takes the smallest (gain, cluster id).
-// Vertices with more than kMaxCand candidate clusters, or whose keys find no
-// slot in the set, are deferred to a list the group scorer finishes in the
-// same pass, so results never depend on these capacities.
+//  2. its arcs are walked in chunks, every thread taking consecutive arcs
+//     with independent loads; each arc whose head lies in another cluster
+//     inserts the key (tail, head cluster) into a tile-wide LDS hash set and
+//     the first insertion of a key counts a candidate for the tail (a
+//     self-loop points at the own cluster and drops out with it);
+//  3. the set is compacted into per-vertex runs of candidate clusters;
+//  4. the pairs (candidate cluster, vertex) and (own cluster, boundary
+//     vertex) form a flat list that groups of kProbeLanes lanes probe,
+//     lanes spread over the partitions, with the next batch's label rows in
+//     flight while the current batch probes;
+//  5. one thread per vertex takes the smallest (gain, cluster id).
+// A vertex whose key finds no slot in the set is deferred to a list that
+// the group scorer finishes in the same pass, so results never depend on
+// the set's capacity.
 // ---------------------------------------------------------------------------
 constexpr int kArcChunk = 1024;
-constexpr int kMaxCand = 8;
 constexpr int kSetSlots = 2048;
 constexpr int kSetProbe = 64;
-constexpr int kPairMax = kBlock * (1 + kMaxCand);
+constexpr int kPairMax = kSetSlots + kBlock;  // every candidate plus one own pair per vertex
 constexpr int kProbeLanes = 16;
 constexpr int kProbeRegs = 64 / kProbeLanes;  // labels per lane when k <= 64
 constexpr int kProbeBatch = 4;
@@ -255,10 +255,13 @@ void k_score_tile(PassArgs a) {
   if (a.ctl->done) return;
   __shared__ int32_t s_off[kBlock + 1];
   __shared__ int32_t s_c[kBlock];
-  __shared__ int32_t s_nc[kBlock];
-  __shared__ int32_t s_cand[kMaxCand * kBlock];  // [slot][vertex]
-  __shared__ int32_t s_pv[kPairMax];             // (vertex << 4) | slot, slot 0 = own
-  __shared__ int32_t s_buf[kPairMax];            // set keys, then agreement sums
+  __shared__ int32_t s_nc[kBlock];    // candidates of each vertex
+  __shared__ int32_t s_def[kBlock];   // 1: vertex deferred to the group scorer
+  __shared__ int32_t s_cur[kBlock];   // fill cursor, then start of the vertex's run
+  __shared__ int32_t s_bv[kBlock];    // boundary vertices of the tile
+  __shared__ int32_t s_set[kSetSlots];
+  __shared__ int32_t s_cl[kSetSlots];  // candidate keys grouped by vertex
+  __shared__ int32_t s_S[kPairMax];    // agreement sums: candidates, then own clusters
   const int t = threadIdx.x;
   const int32_t k = a.k;
   const bool kfits = k <= kProbeRegs * kProbeLanes;
@@ -273,7 +276,8 @@ void k_score_tile(PassArgs a) {
     for (int j = t; j <= nv; j += kBlock) s_off[j] = (int32_t)(a.row_ptr[v0 + j] - a0);
     s_c[t] = t < nv ? a.C[v0 + t] : -1;
     s_nc[t] = 0;
-    for (int j = t; j < kSetSlots; j += kBlock) s_buf[j] = -1;
+    s_def[t] = 0;
+    for (int j = t; j < kSetSlots; j += kBlock) s_set[j] = -1;
     __syncthreads();
     const int32_t A = s_off[nv];
     // each thread takes U consecutive arcs of every chunk: one search for
@@ -312,11 +316,10 @@ void k_score_tile(PassArgs a) {
         uint32_t h = ((uint32_t)key * 2654435761u) >> 21;  // 11 bits: kSetSlots
         bool placed = false;
         for (int q = 0; q < kSetProbe; ++q) {
-          int32_t cur = s_buf[h];
-          if (cur == -1) cur = atomicCAS(&s_buf[h], -1, key);
+          int32_t cur = s_set[h];
+          if (cur == -1) cur = atomicCAS(&s_set[h], -1, key);
           if (cur == -1) {  // first sighting of (lo, x)
-            const int slot = atomicAdd(&s_nc[lo], 1);
-            if (slot < kMaxCand) s_cand[slot * kBlock + lo] = x;
+            atomicAdd(&s_nc[lo], 1);
             placed = true;
             break;
           }
@@ -326,16 +329,18 @@ void k_score_tile(PassArgs a) {
           }
           h = (h + 1) & (kSetSlots - 1);
         }
-        if (!placed) atomicAdd(&s_nc[lo], kMaxCand + 1);  // defer the vertex
+        if (!placed) s_def[lo] = 1;
       }
     }
     __syncthreads();
+    // runs of candidates per vertex and the list of boundary vertices, from
+    // one scan of (candidates << 16 | is boundary)
     const int nc = s_nc[t];
-    const bool over = nc > kMaxCand;
-    const bool is_b = t < nv && nc > 0 && !over;
+    const bool def = t < nv && s_def[t];
+    const bool is_b = t < nv && nc > 0 && !def;
     if (t < nv) {
       const int64_t v = v0 + t;
-      if (over) {
+      if (def) {
         const int32_t slot = atomicAdd(&a.ctl->heavy_count, 1);
         a.heavy[slot] = (int32_t)v;
       } else if (nc == 0) {
@@ -345,26 +350,44 @@ void k_score_tile(PassArgs a) {
         boundary += 1;
       }
     }
-    int32_t npairs;
-    const int32_t ps = block_exclusive_scan(is_b ? 1 + nc : 0, &npairs);
-    if (is_b)
-      for (int j = 0; j <= nc; ++j) s_pv[ps + j] = (t << 4) | j;
+    int32_t tot;
+    const int32_t sc0 = block_exclusive_scan(is_b ? (nc << 16) | 1 : 0, &tot);
+    const int32_t ncand = tot >> 16, nb = tot & 0xffff;
+    const int32_t coff = sc0 >> 16;
+    s_cur[t] = coff;
+    if (is_b) s_bv[sc0 & 0xffff] = t;
     __syncthreads();
-    // probes, software-pipelined: the label rows of the next batch are in
-    // flight while the current batch probes the tables
+    for (int h = t; h < kSetSlots; h += kBlock) {
+      const int32_t key = s_set[h];
+      if (key == -1) continue;
+      const int tv = (int)((uint32_t)key >> 24);
+      if (s_def[tv]) continue;
+      s_cl[atomicAdd(&s_cur[tv], 1)] = key;
+    }
+    __syncthreads();
+    // probes over the pairs: p < ncand candidate pairs, then one own pair
+    // per boundary vertex
+    const int npairs = ncand + nb;
     constexpr int kStride = (kBlock / kProbeLanes) * kProbeBatch;
     auto pair_at = [&](int p, int32_t& x, uint32_t& row) {
       x = -1;
       row = 0;
       if (p < npairs) {
-        const int pv = s_pv[p], tv = pv >> 4, j = pv & 15;
+        int tv;
+        if (p < ncand) {
+          const int32_t key = s_cl[p];
+          tv = (int)((uint32_t)key >> 24);
+          x = key & 0xffffff;
+        } else {
+          tv = s_bv[p - ncand];
+          x = s_c[tv];
+        }
         row = (uint32_t)(v0 + tv) * (uint32_t)k;
-        x = j == 0 ? s_c[tv] : s_cand[(j - 1) * kBlock + tv];
       }
     };
     if (kfits) {
       int32_t xs[kProbeBatch], lab[kProbeBatch][kProbeRegs];
-      uint32_t vs[kProbeBatch];  // row offsets v * k (n * k < 2^31)
+      uint32_t vs[kProbeBatch];
       int p0 = g * kProbeBatch;
 #pragma unroll
       for (int q = 0; q < kProbeBatch; ++q) {
@@ -401,7 +424,7 @@ void k_score_tile(PassArgs a) {
 #pragma unroll
         for (int q = 0; q < kProbeBatch; ++q) {
           const int32_t sq = group_sum<kProbeLanes>(sums[q]);
-          if (lane == 0 && xs[q] >= 0) s_buf[p0 + q] = sq;
+          if (lane == 0 && xs[q] >= 0) s_S[p0 + q] = sq;
         }
 #pragma unroll
         for (int q = 0; q < kProbeBatch; ++q) {
@@ -424,7 +447,7 @@ void k_score_tile(PassArgs a) {
             for (int i = lane; i < k; i += kProbeLanes) sum += a.t.N[cell_t<IL>(a.t, i, x, row[i])];
           }
           const int32_t sq = group_sum<kProbeLanes>(sum);
-          if (lane == 0 && x >= 0) s_buf[p0 + q] = sq;
+          if (lane == 0 && x >= 0) s_S[p0 + q] = sq;
         }
       }
     }
@@ -432,13 +455,13 @@ void k_score_tile(PassArgs a) {
     if (is_b) {
       const int64_t v = v0 + t;
       const int32_t c = s_c[t];
-      const int64_t s_own = s_buf[ps];
-      const int64_t sc = a.s[c];
+      const int64_t s_own = s_S[ncand + (sc0 & 0xffff)];
+      const int64_t scz = a.s[c];
       int64_t bestd = 0;
       int32_t bestx = kNone;
-      for (int j = 0; j < nc; ++j) {
-        const int32_t x = s_cand[j * kBlock + t];
-        int64_t d = 2 * (s_own - (int64_t)s_buf[ps + 1 + j]) + (int64_t)k * ((int64_t)a.s[x] - sc - 1);
+      for (int j = coff; j < coff + nc; ++j) {
+        const int32_t x = s_cl[j] & 0xffffff;
+        int64_t d = 2 * (s_own - (int64_t)s_S[j]) + (int64_t)k * ((int64_t)a.s[x] - scz - 1);
         if (a.literal) d += k;
         if (bestx == kNone || d < bestd || (d == bestd && x < bestx)) {
           bestd = d;
