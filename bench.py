@@ -92,13 +92,28 @@ def bench_batch(args):
              for i in insts]
     outs = [torch.empty(i.n, dtype=torch.int32, device="cuda") for i in insts]
     torch.cuda.synchronize()
+    table, tune_s, untuned = None, 0.0, None
+    if args.tune and args.lanes == 0:
+        # autotune on the workload, then run it with the table; the launch
+        # with the built-in shape is timed too
+        t0 = time.perf_counter()
+        table = mcc.batch_tune(probs)
+        tune_s = time.perf_counter() - t0
+        log(f"tuned on {len(probs)} instances in {tune_s:.1f} s: {table.as_dict()}")
+        mcc.consensus_batch(probs, outs=outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            mcc.consensus_batch(probs, outs=outs)
+        torch.cuda.synchronize()
+        untuned = (time.perf_counter() - t0) / args.steps
+    kw = dict(outs=outs, wg_per_cu=args.wg_per_cu, lanes=args.lanes, tune=table)
     for _ in range(args.warmup):
-        mcc.consensus_batch(probs, outs=outs, wg_per_cu=args.wg_per_cu, lanes=args.lanes)
+        mcc.consensus_batch(probs, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, stats, codes, info = mcc.consensus_batch(probs, outs=outs, wg_per_cu=args.wg_per_cu,
-                                                    lanes=args.lanes)
+        _, stats, codes, info = mcc.consensus_batch(probs, **kw)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / args.steps
     assert all(c == 0 for c in codes)
@@ -122,8 +137,12 @@ def bench_batch(args):
                    "sum_n": int(sum(i.n for i in insts)), "sum_nnz": int(sum(i.nnz for i in insts)),
                    "sum_nk": int(sum(i.n * i.k for i in insts)),
                    "solved_in_persistent_kernel": info["solved_in_batch"],
-                   "candidate_evals": int(evals), "wg_per_cu": args.wg_per_cu,
-                   "lanes": args.lanes},
+                   "candidate_evals": int(evals),
+                   "wg_per_cu": table.wg_per_cu if table is not None else args.wg_per_cu,
+                   "lanes": "autotuned per size bucket" if table is not None else args.lanes},
+        "autotune": None if table is None else {
+            "tuned_on_instances": len(probs), "seconds": tune_s,
+            "untuned_solves_per_s": count / untuned, "table": table.as_dict()},
         "one_at_a_time": {"solves_per_s": count / el1, "seconds": el1,
                           "identical_outputs": bool(same)},
         "speedup_vs_one_at_a_time": el1 / el,
@@ -238,6 +257,8 @@ def main():
     ap.add_argument("--budget-gib", type=int, default=64, help="served: HBM admission budget")
     ap.add_argument("--n", type=int, default=0, help="override the vertex count")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="sbm_batch: skip the autotuner (built-in launch shape)")
     ap.add_argument("--cpu-sample", type=int, default=50_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cache", default="", help="npz file to reuse the generated instance")

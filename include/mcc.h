@@ -177,13 +177,44 @@ typedef struct {
   int32_t* out;
 } mcc_problem;
 
+/*
+ * Launch shape of the batched solver, chosen per size bucket by
+ * mcc_batch_tune.  A bucket holds the instances with
+ * floor(log2(max(n, 1))) == n_log2 and k in the class k_class
+ * (0: k <= 8, 1: k <= 16, 2: k <= 32, 3: k <= 64, 4: k <= 256).
+ */
+#define MCC_TUNE_LANES 5      /* candidate lanes per vertex: 4, 8, 16, 32, 64 */
+#define MCC_TUNE_MAX_BUCKETS 160
+typedef struct {
+  int32_t n_log2;
+  int32_t k_class;
+  int32_t lanes;      /* lanes per vertex chosen for the bucket */
+  int32_t instances;  /* instances of the bucket the choice was measured on */
+  int64_t cells;      /* largest contingency table (int32 cells) seen in it */
+  float ms[MCC_TUNE_LANES]; /* summed per-instance device time for each
+                               candidate lanes value, in the order above
+                               (negative: not measured) */
+  int32_t pad;
+} mcc_tune_entry;
+
+typedef struct {
+  int32_t count;      /* valid entries */
+  int32_t wg_per_cu;  /* resident workgroups per compute unit (1..8) */
+  mcc_tune_entry entry[MCC_TUNE_MAX_BUCKETS];
+} mcc_tune_table;
+
 typedef struct {
   void* stream;       /* hipStream_t or NULL */
   int32_t max_rounds; /* per instance; 0 means 1000 */
   uint32_t flags;     /* MCC_F_LITERAL honoured; others ignored */
-  int32_t lanes;      /* lanes per vertex in the batch scorer: 0 (= 16), 8, 16, 32 */
-  int32_t wg_per_cu;  /* resident workgroups per compute unit: 0 (= 2) .. 8 */
+  int32_t lanes;      /* lanes per vertex for every instance: 4, 8, 16, 32 or 64;
+                         0: per instance from the tune table (`tune`, else
+                         the file `tune_cache_path`, else a built-in rule) */
+  int32_t wg_per_cu;  /* resident workgroups per compute unit: 0 (= the
+                         tune table's, else 2) .. 8 */
   int32_t* status;    /* optional host int32[count]: per-instance return code */
+  const mcc_tune_table* tune;  /* optional host pointer, read only */
+  const char* tune_cache_path; /* optional text file written by mcc_tune_save */
   int32_t solved_in_batch; /* out: instances the persistent kernel finished
                               (the rest went through mcc_consensus) */
   float ms_total;     /* out: wall time of the call on the stream */
@@ -208,6 +239,38 @@ typedef struct {
  */
 int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stats,
                         mcc_batch_opts* opts);
+
+/*
+ * Autotuner of the batched solver (the many-instance launch above).
+ * Solves every problem once per candidate lanes value (4, 8, 16, 32, 64),
+ * each time in one persistent launch whose workgroups time their own
+ * instances, and keeps for each size bucket the lanes value with the
+ * smallest summed time; records per bucket the largest contingency table
+ * seen (the workspace table size of later launches); then times whole
+ * launches at 1, 2, 4 and 8 resident workgroups per compute unit with the
+ * chosen lanes and keeps the fastest, among the values that give every
+ * workgroup two or more problems on average (if fewer than two qualify,
+ * the table keeps 2).  The problems stand for the workload the table is
+ * meant for, at its batch size; their out[] buffers are not written
+ * (results go to scratch).  The choice never changes a result: every lanes
+ * value computes the same output.
+ *
+ *  probs, count  as for mcc_consensus_batch (out may be NULL: it is not
+ *                used); instances with k > 256 are ignored.
+ *  opts          stream, max_rounds and flags are used (may be NULL); if
+ *                tune_cache_path is set the table is also written there.
+ *  table         host output.
+ * Returns 0, MCC_EINVAL (a problem fails the argument checks, table NULL)
+ * or the first error of a launch.
+ */
+int mcc_batch_tune(const mcc_problem* probs, int32_t count, const mcc_batch_opts* opts,
+                   mcc_tune_table* table);
+
+/* Write a tune table as text to `path` / read it back.  Host only.
+ * Returns 0, MCC_EINVAL (NULL argument, unreadable or malformed file,
+ * values out of range) or MCC_EDEVICE (the file cannot be written). */
+int mcc_tune_save(const mcc_tune_table* table, const char* path);
+int mcc_tune_load(mcc_tune_table* table, const char* path);
 
 /* Static text for a return code (for MCC_EDEVICE, the last HIP error seen
  * on this thread). */

@@ -19,7 +19,10 @@ MCC_F_ARC_CACHE = 0x10
 
 # every function include/mcc.h declares
 EXPORTS = ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize",
-           "mcc_consensus_batch", "mcc_strerror")
+           "mcc_consensus_batch", "mcc_batch_tune", "mcc_tune_save", "mcc_tune_load",
+           "mcc_strerror")
+MCC_TUNE_LANES, MCC_TUNE_MAX_BUCKETS = 5, 160
+TUNE_LANES = (4, 8, 16, 32, 64)
 
 
 class Csr(ctypes.Structure):
@@ -54,10 +57,30 @@ class Problem(ctypes.Structure):
                 ("init", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("n_log2", ctypes.c_int32), ("k_class", ctypes.c_int32),
+                ("lanes", ctypes.c_int32), ("instances", ctypes.c_int32),
+                ("cells", ctypes.c_int64), ("ms", ctypes.c_float * MCC_TUNE_LANES),
+                ("pad", ctypes.c_int32)]
+
+
+class TuneTable(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("entry", TuneEntry * MCC_TUNE_MAX_BUCKETS)]
+
+    def as_dict(self):
+        return {"wg_per_cu": self.wg_per_cu,
+                "buckets": [{"n_log2": e.n_log2, "k_class": e.k_class, "lanes": e.lanes,
+                             "instances": e.instances, "cells": e.cells,
+                             "ms": dict(zip(TUNE_LANES, [round(x, 4) for x in e.ms]))}
+                            for e in self.entry[:self.count]]}
+
+
 class BatchOpts(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("max_rounds", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("lanes", ctypes.c_int32),
                 ("wg_per_cu", ctypes.c_int32), ("status", ctypes.c_void_p),
+                ("tune", ctypes.c_void_p), ("tune_cache_path", ctypes.c_char_p),
                 ("solved_in_batch", ctypes.c_int32), ("ms_total", ctypes.c_float)]
 
 
@@ -85,6 +108,13 @@ def lib():
         L.mcc_consensus_batch.argtypes = [ctypes.POINTER(Problem), i32, ctypes.POINTER(Stats),
                                           ctypes.POINTER(BatchOpts)]
         L.mcc_consensus_batch.restype = ctypes.c_int
+        L.mcc_batch_tune.argtypes = [ctypes.POINTER(Problem), i32, ctypes.POINTER(BatchOpts),
+                                     ctypes.POINTER(TuneTable)]
+        L.mcc_batch_tune.restype = ctypes.c_int
+        L.mcc_tune_save.argtypes = [ctypes.POINTER(TuneTable), ctypes.c_char_p]
+        L.mcc_tune_save.restype = ctypes.c_int
+        L.mcc_tune_load.argtypes = [ctypes.POINTER(TuneTable), ctypes.c_char_p]
+        L.mcc_tune_load.restype = ctypes.c_int
         L.mcc_strerror.argtypes = [ctypes.c_int]
         L.mcc_strerror.restype = ctypes.c_char_p
         for f in ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize"):
@@ -190,22 +220,11 @@ def canonicalize(x, out=None, stream=None):
     return out, cl.value
 
 
-def consensus_batch(problems, *, max_rounds=0, flags=0, lanes=0, wg_per_cu=0, stream=None,
-                    outs=None):
-    """Solve many independent instances in one persistent launch.
-
-    problems: sequence of dicts with CUDA tensors ``row_ptr`` (int64),
-    ``col`` (int32), ``labels`` (int32 [k, n]) and optional ``init``.
-    Returns ``(outs, stats, status, info)``: output tensors, per-instance
-    stats dicts, per-instance return codes and the batch call's info
-    (instances finished in the persistent kernel, wall time)."""
-    import torch
+def _problems(problems, outs):
+    """ctypes array of problems plus the tensors it points into."""
     count = len(problems)
     keep = []
     arr = (Problem * max(1, count))()
-    if outs is None:
-        outs = [torch.empty(p["row_ptr"].numel() - 1, dtype=torch.int32,
-                            device=p["row_ptr"].device) for p in problems]
     for j, p in enumerate(problems):
         rp = p["row_ptr"].contiguous()
         col = _dev_i32(p["col"], "col")
@@ -218,15 +237,42 @@ def consensus_batch(problems, *, max_rounds=0, flags=0, lanes=0, wg_per_cu=0, st
         arr[j].labels = ctypes.cast(larr, ctypes.c_void_p)
         arr[j].k = len(rows)
         arr[j].init = ini.data_ptr() if ini is not None else None
-        arr[j].out = outs[j].data_ptr() if n > 0 else None
-    st = (Stats * max(1, count))()
-    status = (ctypes.c_int32 * max(1, count))()
+        arr[j].out = outs[j].data_ptr() if outs is not None and n > 0 else None
+    return arr, keep
+
+
+def _batch_opts(max_rounds, flags, lanes, wg_per_cu, stream, tune, tune_cache_path):
     o = BatchOpts()
     o.stream = _stream_ptr(stream)
     o.max_rounds = max_rounds
     o.flags = flags
     o.lanes = lanes
     o.wg_per_cu = wg_per_cu
+    o.tune = ctypes.cast(ctypes.pointer(tune), ctypes.c_void_p) if tune is not None else None
+    o.tune_cache_path = tune_cache_path.encode() if tune_cache_path else None
+    return o
+
+
+def consensus_batch(problems, *, max_rounds=0, flags=0, lanes=0, wg_per_cu=0, stream=None,
+                    outs=None, tune=None, tune_cache_path=None):
+    """Solve many independent instances in one persistent launch.
+
+    problems: sequence of dicts with CUDA tensors ``row_ptr`` (int64),
+    ``col`` (int32), ``labels`` (int32 [k, n]) and optional ``init``.
+    ``lanes`` 0 takes each instance's lanes per vertex from ``tune`` (a
+    TuneTable), else the table file ``tune_cache_path``, else the built-in
+    rule.  Returns ``(outs, stats, status, info)``: output tensors,
+    per-instance stats dicts, per-instance return codes and the batch call's
+    info (instances finished in the persistent kernel, wall time)."""
+    import torch
+    count = len(problems)
+    if outs is None:
+        outs = [torch.empty(p["row_ptr"].numel() - 1, dtype=torch.int32,
+                            device=p["row_ptr"].device) for p in problems]
+    arr, keep = _problems(problems, outs)
+    st = (Stats * max(1, count))()
+    status = (ctypes.c_int32 * max(1, count))()
+    o = _batch_opts(max_rounds, flags, lanes, wg_per_cu, stream, tune, tune_cache_path)
     o.status = ctypes.cast(status, ctypes.c_void_p)
     rc = lib().mcc_consensus_batch(arr, count, st, ctypes.byref(o))
     codes = [status[j] for j in range(count)]
@@ -234,3 +280,26 @@ def consensus_batch(problems, *, max_rounds=0, flags=0, lanes=0, wg_per_cu=0, st
         _check(rc)
     return outs, [st[j].as_dict() for j in range(count)], codes, \
         {"solved_in_batch": o.solved_in_batch, "ms_total": o.ms_total, "rc": rc}
+
+
+def batch_tune(problems, *, max_rounds=0, flags=0, wg_per_cu=0, stream=None,
+               tune_cache_path=None):
+    """Autotune the batched launch on a sample of a workload: lanes per
+    vertex per size bucket, table size and resident workgroups per compute
+    unit.  Returns a TuneTable (also written to ``tune_cache_path`` if
+    given).  The problems' outputs are not written."""
+    arr, keep = _problems(problems, None)
+    o = _batch_opts(max_rounds, flags, 0, wg_per_cu, stream, None, tune_cache_path)
+    table = TuneTable()
+    _check(lib().mcc_batch_tune(arr, len(problems), ctypes.byref(o), ctypes.byref(table)))
+    return table
+
+
+def tune_save(table, path):
+    _check(lib().mcc_tune_save(ctypes.byref(table), path.encode()))
+
+
+def tune_load(path):
+    table = TuneTable()
+    _check(lib().mcc_tune_load(ctypes.byref(table), path.encode()))
+    return table

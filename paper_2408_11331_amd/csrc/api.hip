@@ -1,6 +1,8 @@
 // Host side of libmcc: argument checks, stream-ordered workspace, the setup
 // sequence and the device-driven pass loop behind the C interface in
 // include/mcc.h.
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -676,18 +678,222 @@ int mcc_canonicalize(const int32_t* in, int32_t* out, int64_t n, int32_t* cluste
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batched solves: host checks, launch shape, one persistent launch.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr int kTuneLanes[MCC_TUNE_LANES] = {4, 8, 16, 32, 64};
+constexpr int64_t kCellsCapMin = (int64_t)1 << 16;
+constexpr int64_t kCellsCapMax = (int64_t)1 << 23;
+
+int n_log2_of(int64_t n) {
+  int b = 0;
+  while (n > 1) {
+    n >>= 1;
+    ++b;
+  }
+  return b;
+}
+
+int k_class_of(int32_t k) { return k <= 8 ? 0 : k <= 16 ? 1 : k <= 32 ? 2 : k <= 64 ? 3 : 4; }
+
+// Lanes per vertex when no tune table covers an instance.  Measured on SBM
+// instances with n in [200, 20000] and k in [8, 64]: more vertices in flight
+// beat more lanes per vertex for every k; 4 lanes lead below about 4096
+// vertices, 8 above.
+int default_lanes(int64_t n) { return n < 4096 ? 4 : 8; }
+
+// The table entry of the instance's bucket, else of the nearest n bucket
+// with the same k class, else null.
+const mcc_tune_entry* tune_lookup(const mcc_tune_table* t, int64_t n, int32_t k) {
+  if (!t) return nullptr;
+  const int nb = n_log2_of(n), kc = k_class_of(k);
+  const mcc_tune_entry* best = nullptr;
+  int bestd = 1 << 30;
+  for (int j = 0; j < t->count && j < MCC_TUNE_MAX_BUCKETS; ++j) {
+    const mcc_tune_entry& e = t->entry[j];
+    if (e.k_class != kc) continue;
+    const int d = std::abs(e.n_log2 - nb);
+    if (d < bestd) {
+      bestd = d;
+      best = &e;
+    }
+  }
+  return best;
+}
+
+int64_t pow2_ceil(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+bool problem_ok(const mcc_problem& p, bool need_out) {
+  const int64_t n = p.g.n;
+  bool ok = p.k >= 1 && n >= 0 && p.g.nnz >= 0 && p.labels &&
+            (int64_t)p.k * n < ((int64_t)1 << 31) && p.g.nnz < ((int64_t)1 << 31) - 1;
+  if (ok && n > 0)
+    ok = device_visible(p.g.row_ptr) && (p.g.nnz == 0 || device_visible(p.g.col)) &&
+         (!need_out || device_visible(p.out)) && (!p.init || device_visible(p.init)) &&
+         labels_ok(p.labels, p.k);
+  return ok;
+}
+
+struct BatchRun {
+  const mcc_problem* probs = nullptr;
+  std::vector<int32_t> ids;      // problems to run
+  std::vector<int32_t> lanes;    // per problem (indexed like probs)
+  std::vector<int32_t*> outs;    // per problem: output buffer override, or null
+  int wgpc = 2;
+  int64_t cells_cap = 0;
+  int32_t max_rounds = 1000;
+  int32_t literal = 0;
+  bool capture = false;
+};
+
+// One persistent launch over run.ids; per-problem results land in hres
+// (indexed like probs); returns the launch's time on the stream in ms.
+float run_batch(const BatchRun& run, int32_t count, hipStream_t st, std::vector<BatchRes>* hres) {
+  Arena ar(st);  // the launch's workspace, released on return
+  const mcc_problem* probs = run.probs;
+  std::vector<const int32_t*> allptr;
+  std::vector<BatchInst> hinst(count);
+  std::vector<int64_t> loff(count, 0);
+  int64_t n_max = 1;
+  int32_t k_max = 1;
+  for (int32_t i : run.ids) {
+    loff[i] = (int64_t)allptr.size();
+    for (int j = 0; j < probs[i].k; ++j) allptr.push_back(probs[i].labels[j]);
+    n_max = std::max<int64_t>(n_max, probs[i].g.n);
+    k_max = std::max<int32_t>(k_max, probs[i].k);
+  }
+  const int32_t** dptrs = ar.get<const int32_t*>((int64_t)std::max<size_t>(1, allptr.size()));
+  if (!allptr.empty()) h2d(dptrs, ar.host(allptr), (int64_t)allptr.size(), st);
+  for (int32_t i : run.ids) {
+    const mcc_problem& p = probs[i];
+    BatchInst b{};
+    b.n = p.g.n;
+    b.nnz = p.g.nnz;
+    b.row_ptr = p.g.row_ptr;
+    b.col = p.g.col;
+    b.labels = dptrs + loff[i];
+    b.init = p.init;
+    b.out = run.outs.empty() || !run.outs[i] ? p.out : run.outs[i];
+    b.k = p.k;
+    b.lanes = run.lanes[i];
+    hinst[i] = b;
+  }
+  // largest estimated work first
+  std::vector<int32_t> order(run.ids);
+  auto work = [&](int32_t i) { return probs[i].g.nnz + probs[i].g.n * (int64_t)probs[i].k; };
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return work(a) > work(b); });
+
+  BatchArgs ba{};
+  BatchWs& w = ba.ws;
+  w.n_max = n_max;
+  w.k_max = k_max;
+  w.flag_cap = 2 * n_max + 1024;
+  w.cells_cap = run.cells_cap;
+  const int64_t slots = std::max<int64_t>(
+      1, std::min<int64_t>((int64_t)run.ids.size(), (int64_t)device_sms() * run.wgpc));
+  w.C = ar.get<int32_t>(slots * n_max);
+  w.rawid = ar.get<int32_t>(slots * n_max);
+  w.prop = ar.get<int32_t>(slots * n_max);
+  w.dprop = ar.get<int64_t>(slots * n_max);
+  w.s = ar.get<int32_t>(slots * n_max);
+  w.owner = ar.get<uint64_t>(slots * n_max);
+  w.Lvm = ar.get<int32_t>(slots * n_max * k_max);
+  w.N = ar.get<int32_t>(slots * w.cells_cap);
+  w.flags = ar.get<int32_t>(slots * w.flag_cap);
+  BatchInst* dinst = ar.get<BatchInst>(count);
+  h2d(dinst, ar.host(hinst), count, st);
+  int32_t* dorder = ar.get<int32_t>((int64_t)order.size());
+  h2d(dorder, ar.host(order), (int64_t)order.size(), st);
+  BatchRes* dres = ar.get<BatchRes>(count);
+  int32_t* dqueue = ar.get<int32_t>(1);
+  ba.inst = dinst;
+  ba.order = dorder;
+  ba.res = dres;
+  ba.queue = dqueue;
+  ba.count = (int32_t)order.size();
+  ba.max_rounds = run.max_rounds;
+  ba.literal = run.literal;
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  struct Ev2 {
+    hipEvent_t a, b;
+    ~Ev2() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evg{e0, e1};
+  // the queue reset and the persistent kernel, as one captured graph
+  // (the legacy default stream cannot be captured: plain launches there)
+  if (run.capture && st) {
+    sync(st);
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    launch_fill_i32(dqueue, 1, 0, st);
+    launch_batch(ba, (int)slots, st);
+    hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (ce == hipSuccess) ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ce == hipSuccess) ce = hipEventRecord(e0, st);
+    if (ce == hipSuccess) ce = hipGraphLaunch(exec, st);
+    if (ce == hipSuccess) ce = hipEventRecord(e1, st);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    HIPCK(ce);
+  } else {
+    launch_fill_i32(dqueue, 1, 0, st);
+    HIPCK(hipEventRecord(e0, st));
+    launch_batch(ba, (int)slots, st);
+    HIPCK(hipEventRecord(e1, st));
+  }
+  hres->assign(count, BatchRes{});
+  d2h(hres->data(), dres, count, st);
+  sync(st);
+  float ms = 0.f;
+  HIPCK(hipEventElapsedTime(&ms, e0, e1));
+  return ms;
+}
+
+int64_t heuristic_cells_cap(const mcc_problem* probs, const std::vector<int32_t>& ids) {
+  int64_t n_max = 1;
+  int32_t k_max = 1;
+  for (int32_t i : ids) {
+    n_max = std::max<int64_t>(n_max, probs[i].g.n);
+    k_max = std::max<int32_t>(k_max, probs[i].k);
+  }
+  return std::min<int64_t>(std::max<int64_t>(n_max * k_max, (int64_t)1 << 18), kCellsCapMax);
+}
+
+}  // namespace
+
+extern "C" {
+
 int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stats,
                         mcc_batch_opts* opts) {
   if (count < 0 || (count > 0 && !probs)) return MCC_EINVAL;
   if (opts && opts->max_rounds < 0) return MCC_EINVAL;
   const int32_t max_rounds = opts && opts->max_rounds > 0 ? opts->max_rounds : 1000;
   const uint32_t flags = opts ? opts->flags : 0u;
-  int lanes = opts ? opts->lanes : 0;
+  const int lanes = opts ? opts->lanes : 0;
   if (!batch_lanes_ok(lanes)) return MCC_EINVAL;
-  if (lanes == 0) lanes = 16;
-  int wgpc = opts && opts->wg_per_cu > 0 ? opts->wg_per_cu : 2;
-  wgpc = std::min(wgpc, 8);
   hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+  // launch shape: the caller's table, else the cache file, else built-in rules
+  const mcc_tune_table* table = opts ? opts->tune : nullptr;
+  mcc_tune_table loaded;
+  if (!table && lanes == 0 && opts && opts->tune_cache_path &&
+      mcc_tune_load(&loaded, opts->tune_cache_path) == MCC_OK)
+    table = &loaded;
+  int wgpc = opts && opts->wg_per_cu > 0 ? opts->wg_per_cu : (table ? table->wg_per_cu : 2);
+  wgpc = std::max(1, std::min(wgpc, 8));
   std::vector<int32_t> status(count, MCC_OK);
   if (stats) memset(stats, 0, sizeof(mcc_stats) * (size_t)count);
   if (opts) {
@@ -700,19 +906,11 @@ int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stat
   std::vector<int32_t> eligible;
   std::vector<int32_t> fallback;
   for (int32_t i = 0; i < count; ++i) {
-    const mcc_problem& p = probs[i];
-    const int64_t n = p.g.n;
-    bool ok = p.k >= 1 && n >= 0 && p.g.nnz >= 0 && p.labels &&
-              (int64_t)p.k * n < ((int64_t)1 << 31) && p.g.nnz < ((int64_t)1 << 31) - 1;
-    if (ok && n > 0)
-      ok = device_visible(p.g.row_ptr) && (p.g.nnz == 0 || device_visible(p.g.col)) &&
-           device_visible(p.out) && (!p.init || device_visible(p.init)) &&
-           labels_ok(p.labels, p.k);
-    if (!ok) {
+    if (!problem_ok(probs[i], true)) {
       status[i] = MCC_EINVAL;
       continue;
     }
-    if (p.k > 256) fallback.push_back(i);
+    if (probs[i].k > 256) fallback.push_back(i);
     else eligible.push_back(i);
   }
 
@@ -732,90 +930,25 @@ int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stat
     HIPCK(hipEventRecord(e0, st));
     std::vector<BatchRes> hres(count);
     if (!eligible.empty()) {
-      std::vector<const int32_t*> allptr;
-      std::vector<BatchInst> hinst(count);
-      std::vector<int64_t> loff(count, 0);
-      int64_t n_max = 1;
-      int32_t k_max = 1;
+      BatchRun run;
+      run.probs = probs;
+      run.ids = eligible;
+      run.lanes.assign(count, 16);
+      int64_t cells = 0;
+      bool covered = table != nullptr;
       for (int32_t i : eligible) {
-        const mcc_problem& p = probs[i];
-        loff[i] = (int64_t)allptr.size();
-        for (int j = 0; j < p.k; ++j) allptr.push_back(p.labels[j]);
-        n_max = std::max<int64_t>(n_max, p.g.n);
-        k_max = std::max<int32_t>(k_max, p.k);
+        const mcc_tune_entry* e = tune_lookup(table, probs[i].g.n, probs[i].k);
+        if (!e) covered = false;
+        else cells = std::max(cells, e->cells);
+        run.lanes[i] = lanes ? lanes : (e ? e->lanes : default_lanes(probs[i].g.n));
       }
-      const int32_t** dptrs = ar.get<const int32_t*>((int64_t)allptr.size());
-      h2d(dptrs, ar.host(allptr), (int64_t)allptr.size(), st);
-      for (int32_t i : eligible) {
-        const mcc_problem& p = probs[i];
-        BatchInst b{};
-        b.n = p.g.n;
-        b.nnz = p.g.nnz;
-        b.row_ptr = p.g.row_ptr;
-        b.col = p.g.col;
-        b.labels = dptrs + loff[i];
-        b.init = p.init;
-        b.out = p.out;
-        b.k = p.k;
-        hinst[i] = b;
-      }
-      // largest estimated work first
-      std::vector<int32_t> order(eligible);
-      auto work = [&](int32_t i) { return probs[i].g.nnz + probs[i].g.n * (int64_t)probs[i].k; };
-      std::stable_sort(order.begin(), order.end(),
-                       [&](int32_t a, int32_t b) { return work(a) > work(b); });
-
-      BatchArgs ba{};
-      BatchWs& w = ba.ws;
-      w.n_max = n_max;
-      w.k_max = k_max;
-      w.flag_cap = 2 * n_max + 1024;
-      w.cells_cap = std::min<int64_t>(std::max<int64_t>(n_max * k_max, 1 << 18), 1 << 23);
-      const int64_t slots =
-          std::max<int64_t>(1, std::min<int64_t>((int64_t)eligible.size(), device_sms() * wgpc));
-      w.C = ar.get<int32_t>(slots * n_max);
-      w.rawid = ar.get<int32_t>(slots * n_max);
-      w.prop = ar.get<int32_t>(slots * n_max);
-      w.dprop = ar.get<int64_t>(slots * n_max);
-      w.s = ar.get<int32_t>(slots * n_max);
-      w.owner = ar.get<uint64_t>(slots * n_max);
-      w.Lvm = ar.get<int32_t>(slots * n_max * k_max);
-      w.N = ar.get<int32_t>(slots * w.cells_cap);
-      w.flags = ar.get<int32_t>(slots * w.flag_cap);
-      BatchInst* dinst = ar.get<BatchInst>(count);
-      h2d(dinst, ar.host(hinst), count, st);
-      int32_t* dorder = ar.get<int32_t>((int64_t)order.size());
-      h2d(dorder, ar.host(order), (int64_t)order.size(), st);
-      BatchRes* dres = ar.get<BatchRes>(count);
-      int32_t* dqueue = ar.get<int32_t>(1);
-      ba.inst = dinst;
-      ba.order = dorder;
-      ba.res = dres;
-      ba.queue = dqueue;
-      ba.count = (int32_t)order.size();
-      ba.max_rounds = max_rounds;
-      ba.literal = (flags & MCC_F_LITERAL) ? 1 : 0;
-      // the queue reset and the persistent kernel, as one captured graph
-      // (the legacy default stream cannot be captured: plain launches there)
-      if (st) {
-        sync(st);
-        hipGraph_t graph = nullptr;
-        hipGraphExec_t exec = nullptr;
-        HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        launch_fill_i32(dqueue, 1, 0, st);
-        launch_batch(ba, lanes, (int)slots, st);
-        hipError_t ce = hipStreamEndCapture(st, &graph);
-        if (ce == hipSuccess) ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (ce == hipSuccess) ce = hipGraphLaunch(exec, st);
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        HIPCK(ce);
-      } else {
-        launch_fill_i32(dqueue, 1, 0, st);
-        launch_batch(ba, lanes, (int)slots, st);
-      }
-      d2h(hres.data(), dres, count, st);
-      sync(st);
+      run.cells_cap = covered ? std::min(kCellsCapMax, std::max(kCellsCapMin, pow2_ceil(cells)))
+                              : heuristic_cells_cap(probs, eligible);
+      run.wgpc = wgpc;
+      run.max_rounds = max_rounds;
+      run.literal = (flags & MCC_F_LITERAL) ? 1 : 0;
+      run.capture = true;
+      run_batch(run, count, st, &hres);
       for (int32_t i : eligible) {
         if (hres[i].status == kBatchTooBig) fallback.push_back(i);
         else if (hres[i].status == kBatchInvalid) status[i] = MCC_EINVAL;
@@ -832,6 +965,7 @@ int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stat
         o.candidate_evals = hres[i].candidate_evals;
         o.objective_init = hres[i].objective_init;
         o.objective = hres[i].objective;
+        o.lanes_used = run.lanes[i];
       }
     }
     for (int32_t i : fallback) {
@@ -856,6 +990,165 @@ int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stat
     if (opts && opts->status) opts->status[i] = status[i];
   }
   return first_err;
+}
+
+int mcc_batch_tune(const mcc_problem* probs, int32_t count, const mcc_batch_opts* opts,
+                   mcc_tune_table* table) {
+  if (!table || count < 0 || (count > 0 && !probs)) return MCC_EINVAL;
+  if (opts && (opts->max_rounds < 0 || !batch_lanes_ok(opts->lanes))) return MCC_EINVAL;
+  memset(table, 0, sizeof *table);
+  table->wg_per_cu = 2;
+  std::vector<int32_t> ids;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!problem_ok(probs[i], false)) return MCC_EINVAL;
+    if (probs[i].k <= 256 && probs[i].g.n > 0) ids.push_back(i);
+  }
+  hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
+  try {
+    int dev = 0;
+    HIPCK(hipGetDevice(&dev));
+    int khz = 0;
+    HIPCK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    const double ms_per_tick = khz > 0 ? 1.0 / khz : 0.0;
+    // bucket of every instance
+    std::vector<int32_t> bucket(count, -1);
+    std::vector<std::pair<int, int>> keys;
+    for (int32_t i : ids) {
+      const std::pair<int, int> key{n_log2_of(probs[i].g.n), k_class_of(probs[i].k)};
+      auto it = std::find(keys.begin(), keys.end(), key);
+      if (it == keys.end()) {
+        if ((int)keys.size() == MCC_TUNE_MAX_BUCKETS) return MCC_EINVAL;
+        keys.push_back(key);
+        it = keys.end() - 1;
+      }
+      bucket[i] = (int32_t)(it - keys.begin());
+    }
+    const int nb = (int)keys.size();
+    table->count = nb;
+    for (int j = 0; j < nb; ++j) {
+      mcc_tune_entry& e = table->entry[j];
+      e.n_log2 = keys[j].first;
+      e.k_class = keys[j].second;
+      e.lanes = 16;
+      for (int c = 0; c < MCC_TUNE_LANES; ++c) e.ms[c] = -1.f;
+    }
+    if (ids.empty()) {
+      if (opts && opts->tune_cache_path) return mcc_tune_save(table, opts->tune_cache_path);
+      return MCC_OK;
+    }
+    Arena ar(st);
+    // results go to scratch
+    int64_t total_n = 0;
+    for (int32_t i : ids) total_n += probs[i].g.n;
+    int32_t* scratch = ar.get<int32_t>(total_n);
+    BatchRun run;
+    run.probs = probs;
+    run.ids = ids;
+    run.outs.assign(count, nullptr);
+    int64_t off = 0;
+    for (int32_t i : ids) {
+      run.outs[i] = scratch + off;
+      off += probs[i].g.n;
+    }
+    run.max_rounds = opts && opts->max_rounds > 0 ? opts->max_rounds : 1000;
+    run.literal = opts && (opts->flags & MCC_F_LITERAL) ? 1 : 0;
+    run.wgpc = opts && opts->wg_per_cu > 0 ? std::min(opts->wg_per_cu, 8) : 2;
+    run.cells_cap = heuristic_cells_cap(probs, ids);  // larger tables still report their size
+    std::vector<BatchRes> hres;
+    std::vector<std::vector<double>> ms(nb, std::vector<double>(MCC_TUNE_LANES, 0.0));
+    std::vector<int32_t> inst(nb, 0);
+    std::vector<int64_t> cells(nb, 0);
+    for (int c = 0; c < MCC_TUNE_LANES; ++c) {
+      run.lanes.assign(count, kTuneLanes[c]);
+      run_batch(run, count, st, &hres);
+      for (int32_t i : ids) {
+        const BatchRes& r = hres[i];
+        const int j = bucket[i];
+        cells[j] = std::max(cells[j], r.cells);
+        if (r.status != 0) continue;
+        ms[j][c] += (double)r.ticks * ms_per_tick;
+        if (c == 0) inst[j] += 1;
+      }
+    }
+    for (int j = 0; j < nb; ++j) {
+      mcc_tune_entry& e = table->entry[j];
+      e.instances = inst[j];
+      e.cells = cells[j];
+      int best = 2;
+      for (int c = 0; c < MCC_TUNE_LANES; ++c) {
+        e.ms[c] = inst[j] ? (float)ms[j][c] : -1.f;
+        if (inst[j] && ms[j][c] < ms[j][best]) best = c;
+      }
+      e.lanes = kTuneLanes[best];
+    }
+    // resident workgroups per compute unit, with the chosen lanes and table size
+    for (int32_t i : ids) run.lanes[i] = table->entry[bucket[i]].lanes;
+    int64_t cmax = 0;
+    for (int j = 0; j < nb; ++j) cmax = std::max(cmax, cells[j]);
+    run.cells_cap = std::min(kCellsCapMax, std::max(kCellsCapMin, pow2_ceil(cmax)));
+    // (only values whose workgroups take two or more instances each on
+    // average: fewer problems than that say nothing about the full workload)
+    std::vector<int> wgs;
+    for (int wg : {1, 2, 4, 8})
+      if ((int64_t)device_sms() * wg * 2 <= (int64_t)ids.size()) wgs.push_back(wg);
+    if (wgs.size() < 2) wgs.clear();
+    float best_ms = -1.f;
+    for (int wg : wgs) {
+      run.wgpc = wg;
+      const float t = run_batch(run, count, st, &hres);
+      if (best_ms < 0.f || t < best_ms) {
+        best_ms = t;
+        table->wg_per_cu = wg;
+      }
+    }
+  } catch (...) {
+    return translate(std::current_exception());
+  }
+  if (opts && opts->tune_cache_path) return mcc_tune_save(table, opts->tune_cache_path);
+  return MCC_OK;
+}
+
+int mcc_tune_save(const mcc_tune_table* t, const char* path) {
+  if (!t || !path || t->count < 0 || t->count > MCC_TUNE_MAX_BUCKETS) return MCC_EINVAL;
+  FILE* f = fopen(path, "w");
+  if (!f) return MCC_EDEVICE;
+  bool ok = fprintf(f, "mcc-tune 1\nwg_per_cu %d\nbuckets %d\n", t->wg_per_cu, t->count) > 0;
+  for (int j = 0; j < t->count && ok; ++j) {
+    const mcc_tune_entry& e = t->entry[j];
+    ok = fprintf(f, "%d %d %d %d %lld", e.n_log2, e.k_class, e.lanes, e.instances,
+                 (long long)e.cells) > 0;
+    for (int c = 0; c < MCC_TUNE_LANES && ok; ++c) ok = fprintf(f, " %.6g", e.ms[c]) > 0;
+    ok = ok && fputc('\n', f) != EOF;
+  }
+  if (fclose(f) != 0) ok = false;
+  return ok ? MCC_OK : MCC_EDEVICE;
+}
+
+int mcc_tune_load(mcc_tune_table* t, const char* path) {
+  if (!t || !path) return MCC_EINVAL;
+  FILE* f = fopen(path, "r");
+  if (!f) return MCC_EINVAL;
+  memset(t, 0, sizeof *t);
+  int version = 0, wg = 0, count = 0;
+  bool ok = fscanf(f, "mcc-tune %d wg_per_cu %d buckets %d", &version, &wg, &count) == 3 &&
+            version == 1 && wg >= 1 && wg <= 8 && count >= 0 && count <= MCC_TUNE_MAX_BUCKETS;
+  for (int j = 0; j < count && ok; ++j) {
+    mcc_tune_entry& e = t->entry[j];
+    long long cells = 0;
+    ok = fscanf(f, "%d %d %d %d %lld", &e.n_log2, &e.k_class, &e.lanes, &e.instances, &cells) == 5;
+    for (int c = 0; c < MCC_TUNE_LANES && ok; ++c) ok = fscanf(f, "%f", &e.ms[c]) == 1;
+    e.cells = cells;
+    ok = ok && e.n_log2 >= 0 && e.n_log2 <= 31 && e.k_class >= 0 && e.k_class <= 4 &&
+         batch_lanes_ok(e.lanes) && e.lanes != 0 && e.cells >= 0 && e.instances >= 0;
+  }
+  fclose(f);
+  if (!ok) {
+    memset(t, 0, sizeof *t);
+    return MCC_EINVAL;
+  }
+  t->count = count;
+  t->wg_per_cu = wg;
+  return MCC_OK;
 }
 
 }  // extern "C"

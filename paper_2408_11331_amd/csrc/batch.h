@@ -14,7 +14,7 @@ struct BatchInst {
   const int32_t* init;           // null: singletons
   int32_t* out;
   int32_t k;
-  int32_t pad;
+  int32_t lanes;  // lanes per vertex in the scorer: 4, 8, 16, 32 or 64
 };
 
 // Per-instance result written by the kernel.
@@ -23,6 +23,8 @@ struct BatchRes {
   int32_t passes, converged, fallback_rounds, clusters;
   int32_t pad;
   int64_t moves, candidate_evals, objective_init, objective;
+  int64_t cells;  // table cells the instance needs (0 if it failed earlier)
+  int64_t ticks;  // device wall-clock ticks the workgroup spent on it
 };
 
 constexpr int32_t kBatchTooBig = 1;
@@ -59,6 +61,6 @@ struct BatchArgs {
 };
 
 bool batch_lanes_ok(int lanes);
-void launch_batch(const BatchArgs& a, int lanes, int grid, hipStream_t st);
+void launch_batch(const BatchArgs& a, int grid, hipStream_t st);
 
 }  // namespace mcc

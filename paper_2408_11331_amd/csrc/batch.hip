@@ -95,7 +95,92 @@ __device__ inline void bmove(int32_t* N, int32_t* s, const int32_t* Lvm, const i
   *ds2 += 2 * (int64_t)o1 * d + 1 - 2 * (int64_t)o2 * d + 1;
 }
 
+// One scoring pass over the instance: G lanes per vertex, kBlock / G
+// vertices at a time.  Candidates are taken in increasing cluster id by
+// repeated group minima, so the result does not depend on G.  Kept out of
+// line: inlined, the five variants share one register allocation and the
+// kernel loses a wave per SIMD.
 template <int G>
+__device__ __attribute__((noinline)) void score_pass(const BatchInst& in, bool literal, const int32_t* C,
+                           const int32_t* Lvm, const int32_t* N, const int32_t* s,
+                           const int64_t* s_toff, const int32_t* s_L, int32_t* prop,
+                           int64_t* dprop, int64_t* evals_out, int32_t* np_out) {
+  constexpr int R = 8;  // arc registers per lane before re-reading memory
+  constexpr int32_t kInf = 0x7fffffff;
+  constexpr int NG = kBlock / G;
+  const int lane = threadIdx.x & (G - 1), grp = threadIdx.x / G;
+  const int64_t n = in.n;
+  const int32_t k = in.k;
+  int64_t evals = 0;
+  int32_t np = 0;
+  for (int64_t v = grp; v < n; v += NG) {
+    const int32_t cv = C[v];
+    const int64_t beg = in.row_ptr[v], end = in.row_ptr[v + 1];
+    const bool fits = end - beg <= (int64_t)G * R;
+    int32_t xr[R];
+    if (fits) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t j = beg + r * G + lane;
+        xr[r] = kInf;
+        if (j < end) {
+          const int32_t cu = C[in.col[j]];
+          if (cu != cv) xr[r] = cu;
+        }
+      }
+    }
+    const int32_t* row = Lvm + v * k;
+    auto agree = [&](int32_t y) -> int32_t {
+      int32_t sum = 0;
+      for (int i = lane; i < k; i += G) sum += N[s_toff[i] + (int64_t)y * s_L[i] + row[i]];
+      return group_sum<G>(sum);
+    };
+    int32_t last = -1, ncand = 0, bestx = kNone;
+    int64_t bestd = 0, s_own = -1;
+    const int64_t sc = s[cv];
+    for (;;) {
+      int32_t mn = kInf;
+      if (fits) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) mn = min(mn, xr[r]);
+      } else {
+        for (int64_t j = beg + lane; j < end; j += G) {
+          const int32_t cu = C[in.col[j]];
+          if (cu != cv && cu > last && cu < mn) mn = cu;
+        }
+      }
+      mn = group_min<G>(mn);
+      if (mn == kInf) break;
+      if (s_own < 0) s_own = agree(cv);
+      const int64_t sx = agree(mn);
+      int64_t d = 2 * (s_own - sx) + (int64_t)k * ((int64_t)s[mn] - sc - 1);
+      if (literal) d += k;
+      if (ncand == 0 || d < bestd) {
+        bestd = d;
+        bestx = mn;
+      }
+      ++ncand;
+      last = mn;
+      if (fits) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (xr[r] == mn) xr[r] = kInf;
+      }
+    }
+    if (lane == 0) {
+      evals += ncand;
+      const bool pp = ncand > 0 && bestd < 0;
+      prop[v] = pp ? bestx : kNone;
+      if (pp) {
+        dprop[v] = bestd;
+        ++np;
+      }
+    }
+  }
+  *evals_out = evals;
+  *np_out = np;
+}
+
 __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
   __shared__ int64_t s_toff[kBatchMaxK + 1];
   __shared__ int32_t s_L[kBatchMaxK];
@@ -103,11 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
   __shared__ int64_t s_r64[kBlock / 64];
   __shared__ int32_t s_idx;
   __shared__ int32_t s_flag;
-  constexpr int R = 8;  // arc registers per lane before re-reading memory
-  constexpr int32_t kInf = 0x7fffffff;
   const int t = threadIdx.x;
-  const int lane = t & (G - 1), grp = t / G;
-  constexpr int NG = kBlock / G;
   // workspace slot of this workgroup
   const int64_t slot = blockIdx.x;
   const BatchWs& w = b.ws;
@@ -130,20 +211,25 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
     const int32_t id = b.order[qi];
     const BatchInst in = b.inst[id];
     BatchRes res = {};
+    const int64_t t0 = wall_clock64();
+    auto report = [&](BatchRes& r) {  // thread 0 only
+      r.ticks = wall_clock64() - t0;
+      b.res[id] = r;
+    };
     const int64_t n = in.n;
     const int32_t k = in.k;
     if (n == 0) {
       if (t == 0) {
         res.passes = 1;
         res.converged = 1;
-        b.res[id] = res;
+        report(res);
       }
       continue;
     }
     if (n > w.n_max || k > w.k_max || n + 1 > w.flag_cap) {
       if (t == 0) {
         res.status = kBatchTooBig;
-        b.res[id] = res;
+        report(res);
       }
       continue;
     }
@@ -162,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
       if (bad) {
         if (t == 0) {
           res.status = kBatchInvalid;
-          b.res[id] = res;
+          report(res);
         }
         continue;
       }
@@ -216,7 +302,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
     if (status) {
       if (t == 0) {
         res.status = status;
-        b.res[id] = res;
+        report(res);
       }
       __syncthreads();
       continue;
@@ -227,10 +313,11 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
       s_flag = s_toff[k] > w.cells_cap;
     }
     __syncthreads();
+    res.cells = s_toff[k];
     if (s_flag) {
       if (t == 0) {
         res.status = kBatchTooBig;
-        b.res[id] = res;
+        report(res);
       }
       __syncthreads();
       continue;
@@ -266,69 +353,13 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
     for (;;) {
       int64_t evals = 0;
       int32_t np = 0;
-      for (int64_t v = grp; v < n; v += NG) {
-        const int32_t cv = C[v];
-        const int64_t beg = in.row_ptr[v], end = in.row_ptr[v + 1];
-        const bool fits = end - beg <= (int64_t)G * R;
-        int32_t xr[R];
-        if (fits) {
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int64_t j = beg + r * G + lane;
-            xr[r] = kInf;
-            if (j < end) {
-              const int32_t cu = C[in.col[j]];
-              if (cu != cv) xr[r] = cu;
-            }
-          }
-        }
-        const int32_t* row = Lvm + v * k;
-        auto agree = [&](int32_t y) -> int32_t {
-          int32_t sum = 0;
-          for (int i = lane; i < k; i += G) sum += N[s_toff[i] + (int64_t)y * s_L[i] + row[i]];
-          return group_sum<G>(sum);
-        };
-        int32_t last = -1, ncand = 0, bestx = kNone;
-        int64_t bestd = 0, s_own = -1;
-        const int64_t sc = s[cv];
-        for (;;) {
-          int32_t mn = kInf;
-          if (fits) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) mn = min(mn, xr[r]);
-          } else {
-            for (int64_t j = beg + lane; j < end; j += G) {
-              const int32_t cu = C[in.col[j]];
-              if (cu != cv && cu > last && cu < mn) mn = cu;
-            }
-          }
-          mn = group_min<G>(mn);
-          if (mn == kInf) break;
-          if (s_own < 0) s_own = agree(cv);
-          const int64_t sx = agree(mn);
-          int64_t d = 2 * (s_own - sx) + (int64_t)k * ((int64_t)s[mn] - sc - 1);
-          if (b.literal) d += k;
-          if (ncand == 0 || d < bestd) {
-            bestd = d;
-            bestx = mn;
-          }
-          ++ncand;
-          last = mn;
-          if (fits) {
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-              if (xr[r] == mn) xr[r] = kInf;
-          }
-        }
-        if (lane == 0) {
-          evals += ncand;
-          const bool pp = ncand > 0 && bestd < 0;
-          prop[v] = pp ? bestx : kNone;
-          if (pp) {
-            dprop[v] = bestd;
-            ++np;
-          }
-        }
+      const bool lit = b.literal != 0;
+      switch (in.lanes) {
+        case 4: score_pass<4>(in, lit, C, Lvm, N, s, s_toff, s_L, prop, dprop, &evals, &np); break;
+        case 8: score_pass<8>(in, lit, C, Lvm, N, s, s_toff, s_L, prop, dprop, &evals, &np); break;
+        case 32: score_pass<32>(in, lit, C, Lvm, N, s, s_toff, s_L, prop, dprop, &evals, &np); break;
+        case 64: score_pass<64>(in, lit, C, Lvm, N, s, s_toff, s_L, prop, dprop, &evals, &np); break;
+        default: score_pass<16>(in, lit, C, Lvm, N, s, s_toff, s_L, prop, dprop, &evals, &np); break;
       }
       evals = wg_reduce(evals, Add64(), s_r64);
       const int64_t nprop = wg_reduce((int64_t)np, Add64(), s_r64);
@@ -403,21 +434,19 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
     ncl = wg_reduce(ncl, Add64(), s_r64);
     res.clusters = (int32_t)ncl;
     res.objective = O;
-    if (t == 0) b.res[id] = res;
+    if (t == 0) report(res);
     __syncthreads();
   }
 }
 
 }  // namespace
 
-bool batch_lanes_ok(int lanes) { return lanes == 0 || lanes == 8 || lanes == 16 || lanes == 32; }
+bool batch_lanes_ok(int lanes) {
+  return lanes == 0 || lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32 || lanes == 64;
+}
 
-void launch_batch(const BatchArgs& a, int lanes, int grid, hipStream_t st) {
-  switch (lanes) {
-    case 8: k_batch<8><<<grid, kBlock, 0, st>>>(a); break;
-    case 32: k_batch<32><<<grid, kBlock, 0, st>>>(a); break;
-    default: k_batch<16><<<grid, kBlock, 0, st>>>(a); break;
-  }
+void launch_batch(const BatchArgs& a, int grid, hipStream_t st) {
+  k_batch<<<grid, kBlock, 0, st>>>(a);
 }
 
 }  // namespace mcc

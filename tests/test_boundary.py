@@ -39,3 +39,44 @@ def test_strerror_is_static_text():
     L = mcc.lib()
     for code in (0, -1, -2, -3, -5, 7):
         assert isinstance(L.mcc_strerror(code), bytes)
+
+
+# ------------------------------------------- tune table files (host only) ---
+def _table():
+    t = mcc.TuneTable()
+    t.count, t.wg_per_cu = 2, 4
+    for j, (nb, kc, lanes, cells) in enumerate([(9, 1, 8, 4096), (14, 3, 32, 1 << 20)]):
+        e = t.entry[j]
+        e.n_log2, e.k_class, e.lanes, e.instances, e.cells = nb, kc, lanes, 3 + j, cells
+        for c in range(mcc.MCC_TUNE_LANES):
+            e.ms[c] = 0.5 * (c + 1) + j
+    return t
+
+
+def test_tune_table_round_trip(tmp_path):
+    if not os.path.exists(mcc.LIB_PATH):
+        pytest.skip("libmcc.so not built")
+    path = str(tmp_path / "tune.txt")
+    mcc.tune_save(_table(), path)
+    back = mcc.tune_load(path)
+    assert back.as_dict() == _table().as_dict()
+
+
+@pytest.mark.parametrize("text", [
+    "",
+    "mcc-tune 2\nwg_per_cu 2\nbuckets 0\n",                       # unknown version
+    "mcc-tune 1\nwg_per_cu 9\nbuckets 0\n",                       # workgroups out of range
+    "mcc-tune 1\nwg_per_cu 2\nbuckets 1\n9 1 12 1 10 1 1 1 1 1\n",  # lanes not offered
+    "mcc-tune 1\nwg_per_cu 2\nbuckets 1\n9 7 8 1 10 1 1 1 1 1\n",   # k class out of range
+    "mcc-tune 1\nwg_per_cu 2\nbuckets 2\n9 1 8 1 10 1 1 1 1 1\n",   # truncated
+])
+def test_tune_table_rejects_malformed(tmp_path, text):
+    if not os.path.exists(mcc.LIB_PATH):
+        pytest.skip("libmcc.so not built")
+    path = tmp_path / "bad.txt"
+    path.write_text(text)
+    with pytest.raises(mcc.MccError) as e:
+        mcc.tune_load(str(path))
+    assert e.value.code == mcc.MCC_EINVAL
+    with pytest.raises(mcc.MccError):
+        mcc.tune_load(str(tmp_path / "missing.txt"))

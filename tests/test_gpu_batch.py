@@ -48,7 +48,7 @@ def instances():
     return out
 
 
-@pytest.mark.parametrize("lanes", [0, 8, 32])
+@pytest.mark.parametrize("lanes", [0, 4, 8, 32, 64])
 def test_batch_equals_single(mcc, lanes):
     import torch
     print(f"[gpu-case] batch lanes={lanes}", flush=True)
@@ -111,3 +111,39 @@ def test_batch_max_rounds_and_literal(mcc):
                                           max_rounds=mr, literal=True)
             assert np.array_equal(out.cpu().numpy(), eo)
             assert st["passes"] == est["passes"] and st["objective"] == est["objective"]
+
+
+def test_autotune_then_tuned_batch(mcc, tmp_path):
+    # the tuner's table (lanes per size bucket, table size, workgroups per
+    # compute unit) changes where and how fast instances run, never results
+    import torch
+    print("[gpu-case] batch autotune", flush=True)
+    items = instances()
+    probs = [to_problem(i, init) for i, init in items]
+    path = str(tmp_path / "tune.txt")
+    table = mcc.batch_tune(probs, tune_cache_path=path)
+    d = table.as_dict()
+    assert 1 <= d["wg_per_cu"] <= 8 and d["buckets"]
+    for b in d["buckets"]:
+        assert b["lanes"] in mcc.TUNE_LANES
+        if b["instances"]:
+            ms = b["ms"]
+            assert all(v >= 0 for v in ms.values()) and ms[b["lanes"]] == min(ms.values())
+    back = mcc.tune_load(path).as_dict()
+    assert back["wg_per_cu"] == d["wg_per_cu"]
+    assert [(b["n_log2"], b["k_class"], b["lanes"], b["cells"]) for b in back["buckets"]] == \
+        [(b["n_log2"], b["k_class"], b["lanes"], b["cells"]) for b in d["buckets"]]
+    ref = [mcc.consensus(p["row_ptr"], p["col"], p["labels"], p["init"]) for p in probs]
+    by_bucket = {(b["n_log2"], b["k_class"]): b["lanes"] for b in d["buckets"]}
+    for kw in ({"tune": table}, {"tune_cache_path": path}):
+        outs, stats, codes, info = mcc.consensus_batch(probs, **kw)
+        torch.cuda.synchronize()
+        assert all(c == 0 for c in codes)
+        for (inst, _), out, st, (o2, st2) in zip(items, outs, stats, ref):
+            assert np.array_equal(out.cpu().numpy(), o2.cpu().numpy())
+            for key in KEYS:
+                assert st[key] == st2[key], key
+            n, k = inst.labels.shape[1], inst.labels.shape[0]
+            if n > 0 and k <= 256 and st["lanes_used"]:
+                kc = 0 if k <= 8 else 1 if k <= 16 else 2 if k <= 32 else 3 if k <= 64 else 4
+                assert st["lanes_used"] == by_bucket[(max(n, 1).bit_length() - 1, kc)]
