@@ -58,6 +58,11 @@ extern "C" {
                                  pass (costs nnz * 8 bytes and a list build;
                                  pays off with many passes; a tuning knob,
                                  results do not depend on it) */
+#define MCC_F_HASH_TABLES 0x20u /* keep the contingency counts in one
+                                   open-addressing hash table even where dense
+                                   tables fit (they are chosen automatically
+                                   when dense tables would not fit or would be
+                                   far larger; results do not depend on it) */
 
 /* CSR graph: row_ptr[n + 1] (int64, row_ptr[0] = 0, non-decreasing,
  * row_ptr[n] = nnz) and col[nnz] (int32 vertex ids in [0, n)).  Arcs are
@@ -103,6 +108,8 @@ typedef struct {
   float ms_score;          /* with MCC_F_PROFILE: summed duration of the
                               scoring kernels of the executed passes */
   int32_t lanes_used;      /* the `lanes` the scoring ran with (0 = tiled) */
+  int32_t tables;          /* contingency table layout used: 0 dense blocked,
+                              1 dense interleaved, 2 hashed */
 } mcc_stats;
 
 /*

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(PKG, "libmcc.so")
 
 MCC_OK, MCC_EINVAL, MCC_EGRAPH, MCC_ENOMEM, MCC_EDEVICE, MCC_ENOTSUP = 0, -1, -2, -3, -4, -5
 MCC_F_VALIDATE, MCC_F_TRACE, MCC_F_LITERAL, MCC_F_PROFILE = 0x1, 0x2, 0x4, 0x8
-MCC_F_ARC_CACHE = 0x10
+MCC_F_ARC_CACHE, MCC_F_HASH_TABLES = 0x10, 0x20
 
 # every function include/mcc.h declares
 EXPORTS = ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize",
@@ -41,12 +41,12 @@ class Stats(ctypes.Structure):
         ("objective_init", ctypes.c_int64), ("objective", ctypes.c_int64),
         ("ms_total", ctypes.c_float), ("ms_passes", ctypes.c_float),
         ("boundary", ctypes.c_int64), ("ms_score", ctypes.c_float),
-        ("lanes_used", ctypes.c_int32),
+        ("lanes_used", ctypes.c_int32), ("tables", ctypes.c_int32),
     ]
 
     OUT = ("passes", "converged", "fallback_rounds", "clusters", "moves", "candidate_evals",
            "objective_init", "objective", "ms_total", "ms_passes", "boundary", "ms_score",
-           "lanes_used")
+           "lanes_used", "tables")
 
     def as_dict(self):
         return {f: getattr(self, f) for f in self.OUT}

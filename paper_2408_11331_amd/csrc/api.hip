@@ -29,6 +29,8 @@ thread_local std::string g_hip_error;
 // largest dense table (sum over partitions of clusters x labels) accepted.
 constexpr int64_t kMaxLabelFlags = (int64_t)1 << 30;
 constexpr int64_t kMaxTableEntries = (int64_t)3 << 29;  // 6 GiB of int32 counts
+// Largest hashed table (16-byte slots; cell ids stay below 2^31).
+constexpr int64_t kMaxHashSlots = (int64_t)1 << 30;
 
 struct HipError {
   hipError_t e;
@@ -170,7 +172,7 @@ Tables blocked_tables(Arena& ar, const Solve& S, const int32_t* Ldev,
   int32_t* N = ar.get<int32_t>(toff[k]);
   launch_fill_i32(N, toff[k], 0, st);
   *total = toff[k];
-  Tables t;
+  Tables t{};
   t.N = N;
   t.toff = dtoff;
   t.L = Ldev;
@@ -222,7 +224,7 @@ void compact_labels_finish(Arena& ar, int64_t n, int32_t k, const std::vector<in
 // vertex-major label rows the passes read.
 void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
                  const int32_t* init, bool want_rows, const mcc_csr* g_validate, Solve* S,
-                 hipStream_t st) {
+                 hipStream_t st, bool force_hash = false) {
   const int32_t k = (int32_t)hptrs.size();
   S->n = n;
   S->k = k;
@@ -275,6 +277,47 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
     maxL = std::max(maxL, Lh[i]);
     sumL += Lh[i];
   }
+  // Hashed tables when the dense ones would not fit, or would be far larger
+  // than the n k keys a hashed table holds at most.
+  const int64_t dense = (int64_t)K0 * sumL;
+  if (force_hash || dense > kMaxTableEntries ||
+      (dense > ((int64_t)1 << 24) && dense > 16 * n * (int64_t)k)) {
+    int bits = 12;
+    while (((int64_t)1 << bits) < 4 * n * (int64_t)k) ++bits;
+    const int64_t slots = (int64_t)1 << bits;
+    if (slots > kMaxHashSlots) throw Status{MCC_ENOTSUP};
+    std::vector<int64_t> poff(k + 1, 0);
+    for (int i = 0; i < k; ++i) poff[i + 1] = poff[i] + Lh[i];
+    int64_t* dpoff = ar.get<int64_t>(k + 1);
+    h2d(dpoff, ar.host(poff), k + 1, st);
+    Tables t{};
+    t.N = ar.get<int32_t>(4 * slots);
+    t.toff = dpoff;
+    t.L = S->lab.L;
+    t.k = k;
+    t.hashed = 1;
+    t.hshift = 64 - bits;
+    t.hmask = (uint64_t)slots - 1;
+    int32_t* hc = ar.get<int32_t>(2);
+    launch_fill_i32(hc, 2, 0, st);
+    t.hocc = hc;
+    t.herr = hc + 1;
+    launch_hash_clear(t, st);
+    launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, t, st);
+    S->t = t;
+    S->maxL = maxL;
+    S->total = slots;
+    if (want_rows) {
+      S->Lvm = ar.get<int32_t>(n * k);
+      launch_label_transpose(S->lab.dlabels, k, n, S->lab.loff, S->lab.fmap, S->Lvm, st);
+    }
+    S->acc = ar.get<int64_t>(3);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(S->acc), 3, 0ull, st);
+    int32_t* hist = ar.get<int32_t>(sumL);
+    launch_objective0_hashed(t, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, S->s, sumL,
+                             hist, S->acc, st);
+    return;
+  }
   // Blocked tables with dense label ids: the final tables when the labels
   // are not aligned; otherwise first built from a sample of the vertices as
   // the source of the alignment (any injective relabelling is exact, so the
@@ -312,7 +355,7 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
     if (cells <= kMaxTableEntries && cells <= 2 * total + ((int64_t)1 << 20)) {
       launch_fmap_update(S->lab.scan, S->lab.loff, dpoff, amap, k, S->lab.max_span,
                          S->lab.fmap, st);
-      Tables it;
+      Tables it{};
       it.N = ar.get<int32_t>(cells);
       launch_fill_i32(it.N, cells, 0, st);
       it.toff = nullptr;
@@ -397,6 +440,7 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
     stats->ms_total = stats->ms_passes = stats->ms_score = 0.f;
     stats->boundary = 0;
     stats->lanes_used = 0;
+    stats->tables = 0;
   }
   if (n == 0) {
     if (stats) {
@@ -430,7 +474,8 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
 
     std::vector<const int32_t*> hptrs(labels, labels + k);
     Solve S;
-    build_solve(ar, hptrs, n, init, true, (flags & MCC_F_VALIDATE) ? g : nullptr, &S, st);
+    build_solve(ar, hptrs, n, init, true, (flags & MCC_F_VALIDATE) ? g : nullptr, &S, st,
+                (flags & MCC_F_HASH_TABLES) != 0);
 
     int64_t* dtrace = nullptr;
     if (flags & MCC_F_TRACE) dtrace = ar.get<int64_t>((int64_t)max_rounds * 4);
@@ -460,7 +505,7 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
       launch_arc_clusters(g->col, nnz, S.C, ac, st);
     }
 
-    PassArgs a;
+    PassArgs a{};
     a.ctl = ctl;
     a.n = n;
     a.k = k;
@@ -479,6 +524,7 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
     a.in_ptr = in_ptr;
     a.in_pos = in_pos;
     a.cells = S.total;
+    a.hflag = S.t.hashed ? ar.get<int32_t>(1) : nullptr;
     a.cn_bytes = S.K0 <= 256 ? 1 : (S.K0 <= 65536 ? 2 : 4);
     if (a.cn_bytes == 4) {
       a.Cn = S.C;
@@ -539,8 +585,11 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
     d2h(&hc, ctl, 1, st);
     int64_t acc[3];
     d2h(acc, S.acc, 3, st);
+    int32_t hash_err = 0;
+    if (S.t.hashed) d2h(&hash_err, S.t.herr, 1, st);
     HIPCK(hipEventRecord(e3, st));
     sync(st);
+    if (hash_err) throw Status{MCC_ENOMEM};  // cannot happen: the table stays half empty
     if (flags & MCC_F_TRACE) {
       memset(stats->trace, 0, sizeof(int64_t) * 4 * (size_t)max_rounds);
       d2h(stats->trace, dtrace, (int64_t)4 * hc.passes, st);
@@ -562,6 +611,7 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
       stats->ms_passes = ms;
       stats->boundary = hc.boundary;
       stats->lanes_used = lanes;
+      stats->tables = S.t.hashed ? 2 : (S.t.interleaved ? 1 : 0);
       if (profile) {
         float tot = 0.f;
         for (int j = 0; j < hc.passes && 2 * j + 1 < (int)pev.size(); ++j) {

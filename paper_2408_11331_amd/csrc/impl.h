@@ -40,29 +40,106 @@ constexpr int32_t kErrNegLabel = 1;
 constexpr int32_t kErrInitRange = 2;
 constexpr int32_t kErrGraph = 4;
 
-// Dense contingency tables N_i(x, l): the number of vertices of consensus
-// cluster x (dense index) whose label id in partition i is l.  Two layouts:
-//  - blocked:     N[toff[i] + x * L[i] + l], one block per partition;
+// Contingency tables N_i(x, l): the number of vertices of consensus cluster
+// x (dense index) whose label id in partition i is l.  Three layouts:
+//  - blocked:     N[toff[i] + x * L[i] + l], one dense block per partition;
 //  - interleaved: N[(x * Lmax + l) * k + i], the k partitions of one
 //    (cluster, label id) pair side by side.  With label ids aligned to the
 //    consensus cluster each label mostly overlaps (any injective relabelling
 //    leaves every count unchanged), the k probes of one vertex and cluster
-//    mostly fall into one cache line.
+//    mostly fall into one cache line;
+//  - hashed: one open-addressing table (linear probing) of 16-byte slots
+//    {uint64 key, int32 count, unused}, key = x << 32 | (toff[i] + l) with
+//    toff[i] the first global label id of partition i, for cluster counts
+//    whose dense tables would not fit (e.g. singleton starts).  Keys are
+//    never removed; a slot whose count drops to 0 stays, and the table is
+//    rebuilt from the partition before it could fill beyond half.
+// A "cell" is the index of one counter: the dense position, or the slot.
 struct Tables {
-  int32_t* N;
-  const int64_t* toff;  // blocked: start of partition i
+  int32_t* N;           // dense: the counts; hashed: the slots as int32 words
+  const int64_t* toff;  // blocked: start of partition i; hashed: label id offset
   const int32_t* L;     // ids of partition i lie in [0, L[i])
   int32_t Lmax;         // interleaved: ids of every partition lie in [0, Lmax)
   int32_t k;
   int32_t interleaved;
+  int32_t hashed;
+  int32_t hshift;       // hashed: 64 - log2(slots)
+  int32_t pad;
+  uint64_t hmask;       // hashed: slots - 1
+  int32_t* hocc;        // hashed: occupied slots
+  int32_t* herr;        // hashed: set if an insert found no slot
 };
 
-// Table cell of (partition i, cluster x, label id l).  Every table holds
+constexpr uint64_t kHashEmpty = ~0ull;
+
+// Dense cell of (partition i, cluster x, label id l).  Every table holds
 // fewer than 2^31 cells (checked when it is sized), so the index is
 // computed in 32 bits.
 __device__ inline uint32_t cell(const Tables& t, int i, int32_t x, int32_t l) {
   return t.interleaved ? ((uint32_t)x * (uint32_t)t.Lmax + (uint32_t)l) * (uint32_t)t.k + i
                        : (uint32_t)t.toff[i] + (uint32_t)x * (uint32_t)t.L[i] + (uint32_t)l;
+}
+
+__device__ inline uint64_t hkey(const Tables& t, int i, int32_t x, int32_t l) {
+  return ((uint64_t)(uint32_t)x << 32) | (uint64_t)(t.toff[i] + l);
+}
+
+__device__ inline uint64_t hstart(const Tables& t, uint64_t key) {
+  return (key * 0x9E3779B97F4A7C15ull) >> t.hshift;  // Fibonacci hashing
+}
+
+// Count stored under `key`, 0 if absent (reads only: the table is frozen).
+__device__ inline int32_t hget(const Tables& t, uint64_t key) {
+  const uint4* H = reinterpret_cast<const uint4*>(t.N);
+  uint64_t h = hstart(t, key);
+  for (uint64_t q = 0; q <= t.hmask; ++q) {
+    const uint4 e = H[h];
+    const uint64_t kk = ((uint64_t)e.y << 32) | e.x;
+    if (kk == key) return (int32_t)e.z;
+    if (kk == kHashEmpty) return 0;
+    h = (h + 1) & t.hmask;
+  }
+  return 0;
+}
+
+// Slot of `key`, claimed if absent.  The table is sized and rebuilt so that
+// it is never more than half full; should no slot be found, *herr is set
+// (the solve then reports an error) and slot 0 is returned.
+__device__ inline uint32_t hslot(const Tables& t, uint64_t key) {
+  unsigned long long* H = reinterpret_cast<unsigned long long*>(t.N);
+  uint64_t h = hstart(t, key);
+  for (uint64_t q = 0; q <= t.hmask; ++q) {
+    const uint64_t kk = H[2 * h];
+    if (kk == key) return (uint32_t)h;
+    if (kk == kHashEmpty) {
+      const uint64_t prev = atomicCAS(&H[2 * h], (unsigned long long)kHashEmpty,
+                                      (unsigned long long)key);
+      if (prev == kHashEmpty) {
+        atomicAdd(t.hocc, 1);
+        return (uint32_t)h;
+      }
+      if (prev == key) return (uint32_t)h;
+    }
+    h = (h + 1) & t.hmask;
+  }
+  atomicOr(t.herr, 1);
+  return 0;
+}
+
+// The counter of a cell.
+__device__ inline int32_t* counter(const Tables& t, uint32_t c) {
+  return t.hashed ? t.N + 4 * (uint64_t)c + 2 : t.N + c;
+}
+
+// Cell of (i, x, l) for an update: the dense position, or the key's slot
+// (claimed if new).
+__device__ inline uint32_t cell_upd(const Tables& t, int i, int32_t x, int32_t l) {
+  return t.hashed ? hslot(t, hkey(t, i, x, l)) : cell(t, i, x, l);
+}
+
+// Count of (i, x, l) for scoring.
+__device__ inline int32_t count_of(const Tables& t, int i, int32_t x, int32_t l) {
+  return t.hashed ? hget(t, hkey(t, i, x, l)) : t.N[cell(t, i, x, l)];
 }
 
 // ---- setup kernels (setup.hip) -------------------------------------------
@@ -105,6 +182,13 @@ void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, con
                        int64_t total_entries,
                        int64_t* acc /* 3 int64: sum s^2, sum hist^2, sum N^2 */,
                        hipStream_t st);
+// Hashed tables: empty every slot; the objective from label histograms
+// (hist: int32[total_labels] scratch) and the slot counts.
+void launch_hash_clear(Tables t, hipStream_t st);
+void launch_objective0_hashed(const Tables& t, const int32_t* const* dlabels, const int64_t* loff,
+                              const int32_t* fmap, int64_t n, int32_t k, int32_t K0,
+                              const int32_t* s, int64_t total_labels, int32_t* hist,
+                              int64_t* acc, hipStream_t st);
 // In-arc lists: in_ptr (exclusive scan of in-degrees, n + 1) and in_pos
 // (arc positions grouped by head vertex); ac[j] = C[col[j]].
 void launch_in_degree(const int32_t* col, int64_t nnz, int32_t* indeg, hipStream_t st);
@@ -149,6 +233,7 @@ struct PassArgs {
   const int32_t* in_ptr;
   const int32_t* in_pos;
   int64_t cells;      // table cells (keys >= cells address cluster sizes)
+  int32_t* hflag;     // hashed tables: 1 while the current pass rebuilds them
   // Narrow copy of C (uint8 when K0 <= 256, uint16 when K0 <= 65536, else
   // C itself) for the per-arc cluster gathers: a few MiB stay resident in
   // every XCD's L2 where the int32 array would not.
@@ -166,10 +251,15 @@ __device__ inline int32_t cn_load_t(const PassArgs& a, int64_t j, int32_t u) {
   return ((const int32_t*)a.Cn)[u];
 }
 
-template <bool IL>
-__device__ inline uint32_t cell_t(const Tables& t, int i, int32_t x, int32_t l) {
-  if (IL) return ((uint32_t)x * (uint32_t)t.Lmax + (uint32_t)l) * (uint32_t)t.k + i;
-  return (uint32_t)t.toff[i] + (uint32_t)x * (uint32_t)t.L[i] + (uint32_t)l;
+// Table layouts as compile-time variants.
+enum TableKind { kBlocked = 0, kInterleaved = 1, kHashed = 2 };
+
+template <int TK>
+__device__ inline int32_t count_t(const Tables& t, int i, int32_t x, int32_t l) {
+  if (TK == kInterleaved)
+    return t.N[((uint32_t)x * (uint32_t)t.Lmax + (uint32_t)l) * (uint32_t)t.k + i];
+  if (TK == kHashed) return hget(t, hkey(t, i, x, l));
+  return t.N[(uint32_t)t.toff[i] + (uint32_t)x * (uint32_t)t.L[i] + (uint32_t)l];
 }
 
 __device__ inline int32_t cn_load(const PassArgs& a, int64_t u) {

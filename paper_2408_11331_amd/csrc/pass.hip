@@ -140,7 +140,18 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
     // S_y(v) summed over the group's lanes
     auto agree = [&](int32_t y) -> int32_t {
       int32_t sum = 0;
-      if (a.t.interleaved) {
+      if (a.t.hashed) {
+        const uint64_t ky = (uint64_t)(uint32_t)y << 32;
+        if (kfits) {  // implies lds_geom
+#pragma unroll
+          for (int t = 0; t < KR; ++t) {
+            int i = lane + t * G;
+            if (i < k) sum += hget(a.t, ky | (uint64_t)(s_toff[i] + lab[t]));
+          }
+        } else {
+          for (int i = lane; i < k; i += G) sum += count_of(a.t, i, y, row[i]);
+        }
+      } else if (a.t.interleaved) {
         const int64_t base = (int64_t)y * a.t.Lmax;
         if (kfits) {
 #pragma unroll
@@ -249,7 +260,7 @@ constexpr int kProbeLanes = 16;
 constexpr int kProbeRegs = 64 / kProbeLanes;  // labels per lane when k <= 64
 constexpr int kProbeBatch = 4;
 
-template <int CN, bool IL>
+template <int CN, int TK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void k_score_tile(PassArgs a) {
   if (a.ctl->done) return;
@@ -417,7 +428,7 @@ void k_score_tile(PassArgs a) {
 #pragma unroll
           for (int r = 0; r < kProbeRegs; ++r) {
             const int i = lane + r * kProbeLanes;
-            if (xs[q] >= 0 && i < k) sum += a.t.N[cell_t<IL>(a.t, i, xs[q], lab[q][r])];
+            if (xs[q] >= 0 && i < k) sum += count_t<TK>(a.t, i, xs[q], lab[q][r]);
           }
           sums[q] = sum;
         }
@@ -444,7 +455,7 @@ void k_score_tile(PassArgs a) {
           int32_t sum = 0;
           if (x >= 0) {
             const int32_t* row = a.Lvm + ro;
-            for (int i = lane; i < k; i += kProbeLanes) sum += a.t.N[cell_t<IL>(a.t, i, x, row[i])];
+            for (int i = lane; i < k; i += kProbeLanes) sum += count_t<TK>(a.t, i, x, row[i]);
           }
           const int32_t sq = group_sum<kProbeLanes>(sum);
           if (lane == 0 && x >= 0) s_S[p0 + q] = sq;
@@ -514,8 +525,8 @@ __device__ inline int64_t move_counts(const PassArgs& a, int64_t v, int32_t from
   const int32_t* row = a.Lvm + v * a.k;
   for (int i = lane; i < a.k; i += 64) {
     const int32_t l = row[i];
-    int32_t o1 = atomicAdd(&a.t.N[cell(a.t, i, to, l)], d);
-    int32_t o2 = atomicAdd(&a.t.N[cell(a.t, i, from, l)], -d);
+    int32_t o1 = atomicAdd(counter(a.t, cell_upd(a.t, i, to, l)), d);
+    int32_t o2 = atomicAdd(counter(a.t, cell_upd(a.t, i, from, l)), -d);
     acc += 2 * (int64_t)o1 * d + 1 - 2 * (int64_t)o2 * d + 1;
   }
   if (lane == 0) {
@@ -555,7 +566,7 @@ __device__ inline void agg_add(int32_t* hkey, int32_t* hval, const PassArgs& a, 
     h = (h + 1) & (kHashSlots - 1);
   }
   if (key < a.cells) {
-    const int32_t old = atomicAdd(&a.t.N[key], d);
+    const int32_t old = atomicAdd(counter(a.t, (uint32_t)key), d);
     *dn2 += 2 * (int64_t)old * d + 1;
   } else {
     const int32_t old = atomicAdd(&a.s[key - a.cells], d);
@@ -590,8 +601,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
       const int32_t* row = a.Lvm + w * a.k;
       for (int i = lane; i < a.k; i += 64) {
         const int32_t l = row[i];
-        agg_add(hkey, hval, a, cell(a.t, i, to, l), +1, &dn2, &ds2);
-        agg_add(hkey, hval, a, cell(a.t, i, from, l), -1, &dn2, &ds2);
+        agg_add(hkey, hval, a, cell_upd(a.t, i, to, l), +1, &dn2, &ds2);
+        agg_add(hkey, hval, a, cell_upd(a.t, i, from, l), -1, &dn2, &ds2);
       }
       if (lane == 0) {
         agg_add(hkey, hval, a, a.cells + to, +1, &dn2, &ds2);
@@ -604,7 +615,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
     const int32_t key = hkey[j], d = hval[j];
     if (key < 0 || d == 0) continue;
     if (key < a.cells) {
-      const int32_t old = atomicAdd(&a.t.N[key], d);
+      const int32_t old = atomicAdd(counter(a.t, (uint32_t)key), d);
       dn2 += 2 * (int64_t)old * d + (int64_t)d * d;
     } else {
       const int32_t old = atomicAdd(&a.s[key - a.cells], d);
@@ -707,6 +718,42 @@ __global__ __launch_bounds__(kBlock) void k_apply(PassArgs a) {
   }
 }
 
+// Hashed tables: before the batch is applied, rebuild the table from the
+// partition (the counts are a function of C alone) if the keys the batch may
+// add could take it beyond half full.  The batch adds at most k keys per
+// proposal; the table holds 4 n k slots or more and at most n k live keys, so
+// after a rebuild there is always room.
+__global__ void k_hash_guard(PassArgs a, int64_t limit) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) {
+    *a.hflag = 0;
+    return;
+  }
+  const bool need = (int64_t)*a.t.hocc + (int64_t)a.k * ctl->nprop > limit;
+  *a.hflag = need ? 1 : 0;
+  if (need) *a.t.hocc = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hash_reset(PassArgs a) {
+  if (!*a.hflag) return;
+  uint4* H = reinterpret_cast<uint4*>(a.t.N);
+  const uint4 empty = make_uint4(0xffffffffu, 0xffffffffu, 0u, 0u);
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j <= (int64_t)a.t.hmask;
+       j += (int64_t)gridDim.x * kBlock)
+    H[j] = empty;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hash_refill(PassArgs a) {
+  if (!*a.hflag) return;
+  const int64_t total = a.n * a.k;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < total;
+       j += (int64_t)gridDim.x * kBlock) {
+    const int64_t v = j / a.k;
+    const int i = (int)(j - v * a.k);
+    atomicAdd(counter(a.t, hslot(a.t, hkey(a.t, i, a.C[v], a.Lvm[j]))), 1);
+  }
+}
+
 __global__ void k_decide(Ctl* ctl) {
   if (ctl->done) return;
   const int64_t dO = (int64_t)ctl->k * ctl->dS2 - 2 * ctl->dN2;
@@ -758,6 +805,14 @@ void launch_score(const PassArgs& a, int grid, hipStream_t st) {
   k_score<G, false><<<grid, kBlock, 0, st>>>(a);
 }
 
+template <int TK>
+void launch_tile(const PassArgs& a, int grid, hipStream_t st) {
+  if (a.ac) k_score_tile<0, TK><<<grid, kBlock, 0, st>>>(a);
+  else if (a.cn_bytes == 1) k_score_tile<1, TK><<<grid, kBlock, 0, st>>>(a);
+  else if (a.cn_bytes == 2) k_score_tile<2, TK><<<grid, kBlock, 0, st>>>(a);
+  else k_score_tile<4, TK><<<grid, kBlock, 0, st>>>(a);
+}
+
 }  // namespace
 
 bool score_lanes_ok(int lanes) {
@@ -774,19 +829,9 @@ void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, 
   if (score_begin) (void)hipEventRecord(score_begin, st);
   switch (lanes) {
     case 0:
-      if (a.ac) {
-        if (a.t.interleaved) k_score_tile<0, true><<<grid_score, kBlock, 0, st>>>(a);
-        else k_score_tile<0, false><<<grid_score, kBlock, 0, st>>>(a);
-      } else if (a.cn_bytes == 1) {
-        if (a.t.interleaved) k_score_tile<1, true><<<grid_score, kBlock, 0, st>>>(a);
-        else k_score_tile<1, false><<<grid_score, kBlock, 0, st>>>(a);
-      } else if (a.cn_bytes == 2) {
-        if (a.t.interleaved) k_score_tile<2, true><<<grid_score, kBlock, 0, st>>>(a);
-        else k_score_tile<2, false><<<grid_score, kBlock, 0, st>>>(a);
-      } else {
-        if (a.t.interleaved) k_score_tile<4, true><<<grid_score, kBlock, 0, st>>>(a);
-        else k_score_tile<4, false><<<grid_score, kBlock, 0, st>>>(a);
-      }
+      if (a.t.hashed) launch_tile<kHashed>(a, grid_score, st);
+      else if (a.t.interleaved) launch_tile<kInterleaved>(a, grid_score, st);
+      else launch_tile<kBlocked>(a, grid_score, st);
       // deferred vertices: one per wave, as many waves as the chip holds
       k_score<64, true><<<grid_score, kBlock, 0, st>>>(a);
       break;
@@ -798,6 +843,11 @@ void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, 
   }
   if (score_end) (void)hipEventRecord(score_end, st);
   k_begin<<<1, 1, 0, st>>>(a.ctl);
+  if (a.t.hashed) {
+    k_hash_guard<<<1, 1, 0, st>>>(a, (int64_t)((a.t.hmask + 1) / 2));
+    k_hash_reset<<<grid_apply, kBlock, 0, st>>>(a);
+    k_hash_refill<<<grid_apply, kBlock, 0, st>>>(a);
+  }
   k_apply_all<<<grid_apply, kBlock, 0, st>>>(a);
   k_decide<<<1, 1, 0, st>>>(a.ctl);
   k_apply<kCommitOrElect><<<grid_apply, kBlock, 0, st>>>(a);

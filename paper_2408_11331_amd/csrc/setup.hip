@@ -236,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
   const int i = blockIdx.y;
   const int32_t Li = t.L[i];
   const int64_t entries = (int64_t)K0 * Li;
-  const bool lds = entries <= kLdsHist;
+  const bool lds = !t.hashed && entries <= kLdsHist;
   if (lds) {
     for (int j = threadIdx.x; j < entries; j += kBlock) h[j] = 0;
     __syncthreads();
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
     const int64_t v = j * stride;
     const int32_t x = C[v], l = map[p[v]];
     if (lds) atomicAdd(&h[x * Li + l], 1);
-    else atomicAdd(&t.N[cell(t, i, x, l)], 1);
+    else atomicAdd(counter(t, cell_upd(t, i, x, l)), 1);
   }
   if (lds) {
     __syncthreads();
@@ -305,6 +305,38 @@ __global__ __launch_bounds__(kBlock) void k_hist_sumsq(Tables t, int32_t K0,
     int64_t h = 0;
     for (int32_t x = 0; x < K0; ++x) h += t.N[cell(t, i, x, (int32_t)l)];
     s += h * h;
+  }
+  s = block_sum<int64_t>(s);
+  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)acc, (unsigned long long)s);
+}
+
+// ---- hashed tables ---------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_hash_clear(Tables t) {
+  uint4* H = reinterpret_cast<uint4*>(t.N);
+  const uint4 empty = make_uint4(0xffffffffu, 0xffffffffu, 0u, 0u);
+  for (int64_t j = gtid(); j <= (int64_t)t.hmask; j += gstride()) H[j] = empty;
+}
+
+// hist[toff[i] + l] = |P_i l| (label ids in the hashed key space)
+__global__ __launch_bounds__(kBlock) void k_label_hist(const int32_t* const* __restrict__ labels,
+                                                       const int64_t* __restrict__ loff,
+                                                       const int32_t* __restrict__ fmap,
+                                                       const int64_t* __restrict__ toff, int64_t n,
+                                                       int32_t* __restrict__ hist) {
+  const int i = blockIdx.y;
+  const int32_t* p = labels[i];
+  const int32_t* map = fmap + loff[i];
+  int32_t* hi = hist + toff[i];
+  for (int64_t v = gtid(); v < n; v += gstride()) atomicAdd(&hi[map[p[v]]], 1);
+}
+
+// sum of squared slot counts
+__global__ __launch_bounds__(kBlock) void k_slot_sumsq(Tables t, int64_t* __restrict__ acc) {
+  const uint4* H = reinterpret_cast<const uint4*>(t.N);
+  int64_t s = 0;
+  for (int64_t j = gtid(); j <= (int64_t)t.hmask; j += gstride()) {
+    const int64_t c = (int32_t)H[j].z;
+    s += c * c;
   }
   s = block_sum<int64_t>(s);
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)acc, (unsigned long long)s);
@@ -571,6 +603,22 @@ void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, con
   dim3 g(grid_for(maxL, kBlock, 64), k);
   k_hist_sumsq<<<g, kBlock, 0, st>>>(t, K0, acc + 1);
   k_sumsq<<<grid_for(total_entries, kBlock, 2048), kBlock, 0, st>>>(t.N, total_entries, acc + 2);
+}
+
+void launch_hash_clear(Tables t, hipStream_t st) {
+  k_hash_clear<<<grid_for((int64_t)t.hmask + 1, kBlock * 4, 4096), kBlock, 0, st>>>(t);
+}
+
+void launch_objective0_hashed(const Tables& t, const int32_t* const* dlabels, const int64_t* loff,
+                              const int32_t* fmap, int64_t n, int32_t k, int32_t K0,
+                              const int32_t* s, int64_t total_labels, int32_t* hist,
+                              int64_t* acc, hipStream_t st) {
+  k_sumsq<<<grid_for(K0, kBlock, 1024), kBlock, 0, st>>>(s, K0, acc);
+  launch_fill_i32(hist, total_labels, 0, st);
+  dim3 g(grid_for(n, kBlock * 16, 64), k);
+  k_label_hist<<<g, kBlock, 0, st>>>(dlabels, loff, fmap, t.toff, n, hist);
+  k_sumsq<<<grid_for(total_labels, kBlock, 2048), kBlock, 0, st>>>(hist, total_labels, acc + 1);
+  k_slot_sumsq<<<grid_for((int64_t)t.hmask + 1, kBlock * 4, 4096), kBlock, 0, st>>>(t, acc + 2);
 }
 
 void launch_in_degree(const int32_t* col, int64_t nnz, int32_t* indeg, hipStream_t st) {
