@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--budget-gib", type=int, default=64, help="served: HBM admission budget")
     ap.add_argument("--n", type=int, default=0, help="override the vertex count")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--init", default="p0", choices=["p0", "singleton"],
+                    help="consensus start: input partition 0, or singletons (the paper's)")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="sbm_batch: skip the autotuner (built-in launch shape)")
     ap.add_argument("--cpu-sample", type=int, default=50_000)
@@ -290,6 +292,8 @@ def main():
     inst = make_workload(args.workload, args.n, dev, args.cache or None)
     log(f"generated n={inst.n} nnz={inst.nnz} k={inst.k} in {time.perf_counter() - t0:.1f} s")
     D = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    if args.init == "singleton":
+        inst.init = np.arange(inst.n, dtype=np.int32)  # same result as passing no init
     rp, col, lab, ini = D(inst.row_ptr), D(inst.col), D(inst.labels), D(inst.init)
     out = torch.empty(inst.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
@@ -342,7 +346,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": args.workload, "n": inst.n, "nnz": inst.nnz, "k": inst.k,
-            "init": "input partition 0", "passes": passes, "moves": st_ref["moves"],
+            "init": "input partition 0" if args.init == "p0" else "singletons",
+            "tables": ["dense blocked", "dense interleaved", "hashed"][st_ref["tables"]],
+            "passes": passes, "moves": st_ref["moves"],
             "candidate_evals_per_solve": st_ref["candidate_evals"],
             "boundary_vertex_passes": st_ref["boundary"], "objective": st_ref["objective"],
             "lanes_per_vertex": st_ref["lanes_used"],
