@@ -46,7 +46,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC",
-                               "-shared", SRC, "-o", tmp])
+                               "-shared", SRC, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
 
@@ -68,8 +68,13 @@ def lib():
         L.mccref_score.argtypes = [p, p, i64, p, i32, p, i64, i64, i32, p, p, p]
         L.mccref_consensus.argtypes = [p, p, i64, p, i32, p, p, p, p]
         L.mccref_canonicalize.argtypes = [p, p, i64, p]
+        L.mccref_compare.argtypes = [p, p, i64, p]
+        L.mccref_split_join_matrix.argtypes = [p, i32, i64, p]
+        L.mccref_group.argtypes = [p, i32, i64, p, p]
+        L.mccref_elbow_lambda.argtypes = [p, i32, p]
         for f in ("mccref_mirkin", "mccref_objective", "mccref_delta", "mccref_score",
-                  "mccref_consensus", "mccref_canonicalize"):
+                  "mccref_consensus", "mccref_canonicalize", "mccref_compare",
+                  "mccref_split_join_matrix", "mccref_group", "mccref_elbow_lambda"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -160,3 +165,46 @@ def canonicalize(a):
     cl = np.zeros(1, np.int32)
     _check(lib().mccref_canonicalize(_ptr(a), out.ctypes.data, a.size, cl.ctypes.data))
     return out[: a.size], int(cl[0])
+
+
+class _Comparison(ctypes.Structure):
+    _fields_ = [("mirkin", ctypes.c_int64), ("split_join_ab", ctypes.c_int64),
+                ("split_join_ba", ctypes.c_int64), ("split_join", ctypes.c_int64),
+                ("rand", ctypes.c_double), ("vi", ctypes.c_double),
+                ("clusters_a", ctypes.c_int32), ("clusters_b", ctypes.c_int32)]
+
+
+def compare(a, b) -> dict:
+    """Mirkin, split-join (both directions and their sum), Rand distance and
+    variation of information between two partitions (Results, "Evaluation
+    metrics")."""
+    a, b = _i32(a), _i32(b)
+    r = _Comparison()
+    _check(lib().mccref_compare(_ptr(a), _ptr(b), a.size, ctypes.byref(r)))
+    return {f: getattr(r, f) for f, _ in r._fields_}
+
+
+def split_join_matrix(labels) -> np.ndarray:
+    """k x k split-join distances between the input partitions."""
+    labels = _i32(labels)
+    k, n = labels.shape
+    d = np.zeros((k, k), np.int64)
+    _check(lib().mccref_split_join_matrix(_ptr(labels), k, n, d.ctypes.data))
+    return d
+
+
+def group(dist, lam):
+    """Connected components of the partitions linked at distance <= lam."""
+    dist = np.ascontiguousarray(dist, np.int64)
+    k = dist.shape[0]
+    g = np.zeros(k, np.int32)
+    ng = ctypes.c_int32(0)
+    _check(lib().mccref_group(dist.ctypes.data, k, int(lam), g.ctypes.data, ctypes.byref(ng)))
+    return g, ng.value
+
+
+def elbow_lambda(dist) -> int:
+    dist = np.ascontiguousarray(dist, np.int64)
+    lam = ctypes.c_int64(0)
+    _check(lib().mccref_elbow_lambda(dist.ctypes.data, dist.shape[0], ctypes.byref(lam)))
+    return lam.value

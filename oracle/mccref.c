@@ -10,6 +10,7 @@
  */
 #include "mccref.h"
 
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -431,5 +432,183 @@ int mccref_canonicalize(const int32_t* in, int32_t* out, int64_t n, int32_t* clu
   }
   if (clusters) *clusters = next;
   free(map);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Partition comparison (Results, "Evaluation metrics")                      */
+/* ------------------------------------------------------------------------ */
+/* Sum over runs of equal values in the sorted keys of f(run length). */
+static double sum_runs_xlogx(const int64_t* keys, int64_t n) {
+  double total = 0.0;
+  int64_t run = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    if (j > 0 && keys[j] != keys[j - 1]) {
+      total += (double)run * log((double)run);
+      run = 0;
+    }
+    ++run;
+  }
+  if (n > 0) total += (double)run * log((double)run);
+  return total;
+}
+
+static int32_t count_runs(const int64_t* keys, int64_t n) {
+  int32_t runs = 0;
+  for (int64_t j = 0; j < n; ++j)
+    if (j == 0 || keys[j] != keys[j - 1]) ++runs;
+  return runs;
+}
+
+/* Keys (x, y) sorted: sum over x of the largest count of one (x, y) pair. */
+static int64_t sum_of_row_maxima(const int64_t* keys, int64_t n) {
+  int64_t total = 0, best = 0, run = 0;
+  for (int64_t j = 0; j < n; ++j) {
+    if (j > 0 && keys[j] != keys[j - 1]) {
+      if (run > best) best = run;
+      run = 0;
+      if ((keys[j] >> 32) != (keys[j - 1] >> 32)) { /* next row */
+        total += best;
+        best = 0;
+      }
+    }
+    ++run;
+  }
+  if (n > 0) {
+    if (run > best) best = run;
+    total += best;
+  }
+  return total;
+}
+
+static void compare_plain(const int32_t* a, const int32_t* b, int64_t n, int64_t* buf,
+                          mccref_comparison* r) {
+  memset(r, 0, sizeof *r);
+  if (n == 0) return;
+  r->mirkin = mirkin_plain(a, b, n, buf);
+  /* cluster sizes and sum |A| ln |A|, sum |B| ln |B| */
+  for (int64_t j = 0; j < n; ++j) buf[j] = a[j];
+  qsort(buf, (size_t)n, sizeof(int64_t), cmp_i64);
+  const double ha = sum_runs_xlogx(buf, n);
+  r->clusters_a = count_runs(buf, n);
+  for (int64_t j = 0; j < n; ++j) buf[j] = b[j];
+  qsort(buf, (size_t)n, sizeof(int64_t), cmp_i64);
+  const double hb = sum_runs_xlogx(buf, n);
+  r->clusters_b = count_runs(buf, n);
+  /* intersections, grouped by the cluster of a, then by the cluster of b */
+  for (int64_t j = 0; j < n; ++j) buf[j] = pair_key(a[j], b[j]);
+  qsort(buf, (size_t)n, sizeof(int64_t), cmp_i64);
+  const double hab = sum_runs_xlogx(buf, n);
+  r->split_join_ab = n - sum_of_row_maxima(buf, n);
+  for (int64_t j = 0; j < n; ++j) buf[j] = pair_key(b[j], a[j]);
+  qsort(buf, (size_t)n, sizeof(int64_t), cmp_i64);
+  r->split_join_ba = n - sum_of_row_maxima(buf, n);
+  r->split_join = r->split_join_ab + r->split_join_ba;
+  /* VI = H(A) + H(B) - 2 I(A; B) = (sum |A| ln|A| + sum |B| ln|B|
+   *      - 2 sum |A n B| ln|A n B|) / n */
+  r->vi = (ha + hb - 2.0 * hab) / (double)n;
+  r->rand = n > 1 ? (double)r->mirkin / ((double)n * (double)(n - 1)) : 0.0;
+}
+
+int mccref_compare(const int32_t* a, const int32_t* b, int64_t n, mccref_comparison* r) {
+  if (!r || n < 0 || (n > 0 && (!a || !b))) return MCCREF_EINVAL;
+  if (!labels_ok(a, n) || !labels_ok(b, n)) return MCCREF_EINVAL;
+  int64_t* buf = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  if (!buf) return MCCREF_ENOMEM;
+  compare_plain(a, b, n, buf, r);
+  free(buf);
+  return 0;
+}
+
+int mccref_split_join_matrix(const int32_t* labels, int32_t k, int64_t n, int64_t* dist) {
+  if (!dist || k < 1 || n < 0 || (n > 0 && !labels)) return MCCREF_EINVAL;
+  if (!labels_ok(labels, (int64_t)k * n)) return MCCREF_EINVAL;
+  int64_t* buf = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  if (!buf) return MCCREF_ENOMEM;
+  for (int32_t i = 0; i < k; ++i) {
+    dist[(int64_t)i * k + i] = 0;
+    for (int32_t j = i + 1; j < k; ++j) {
+      mccref_comparison r;
+      compare_plain(labels + (int64_t)i * n, labels + (int64_t)j * n, n, buf, &r);
+      dist[(int64_t)i * k + j] = r.split_join;
+      dist[(int64_t)j * k + i] = r.split_join;
+    }
+  }
+  free(buf);
+  return 0;
+}
+
+/* Components of the graph on k partitions with an edge where the distance
+ * is at most lambda: a plain depth-first search from each unvisited
+ * partition in increasing order. */
+static int32_t components(const int64_t* dist, int32_t k, int64_t lambda, int32_t* group,
+                          int32_t* stack) {
+  int32_t ng = 0;
+  for (int32_t i = 0; i < k; ++i) group[i] = -1;
+  for (int32_t s = 0; s < k; ++s) {
+    if (group[s] >= 0) continue;
+    int32_t top = 0;
+    stack[top++] = s;
+    group[s] = ng;
+    while (top > 0) {
+      const int32_t u = stack[--top];
+      for (int32_t w = 0; w < k; ++w)
+        if (group[w] < 0 && dist[(int64_t)u * k + w] <= lambda) {
+          group[w] = ng;
+          stack[top++] = w;
+        }
+    }
+    ++ng;
+  }
+  return ng;
+}
+
+int mccref_group(const int64_t* dist, int32_t k, int64_t lambda, int32_t* group,
+                 int32_t* ngroups) {
+  if (!dist || !group || !ngroups || k < 1) return MCCREF_EINVAL;
+  int32_t* stack = (int32_t*)malloc((size_t)k * sizeof(int32_t));
+  if (!stack) return MCCREF_ENOMEM;
+  *ngroups = components(dist, k, lambda, group, stack);
+  free(stack);
+  return 0;
+}
+
+int mccref_elbow_lambda(const int64_t* dist, int32_t k, int64_t* lambda) {
+  if (!dist || !lambda || k < 1) return MCCREF_EINVAL;
+  *lambda = 0;
+  if (k < 2) return 0;
+  const int64_t m_all = (int64_t)k * (k - 1) / 2;
+  int64_t* t = (int64_t*)malloc((size_t)m_all * sizeof(int64_t));
+  int32_t* group = (int32_t*)malloc((size_t)k * sizeof(int32_t));
+  int32_t* stack = (int32_t*)malloc((size_t)k * sizeof(int32_t));
+  if (!t || !group || !stack) {
+    free(t); free(group); free(stack);
+    return MCCREF_ENOMEM;
+  }
+  int64_t m = 0;
+  for (int32_t i = 0; i < k; ++i)
+    for (int32_t j = i + 1; j < k; ++j) t[m++] = dist[(int64_t)i * k + j];
+  qsort(t, (size_t)m, sizeof(int64_t), cmp_i64);
+  int64_t d = 0; /* distinct values */
+  for (int64_t j = 0; j < m; ++j)
+    if (j == 0 || t[j] != t[d - 1]) t[d++] = t[j];
+  *lambda = t[0];
+  if (d >= 3) {
+    const double g0 = components(dist, k, t[0], group, stack);
+    const double g1 = components(dist, k, t[d - 1], group, stack);
+    if (g0 != g1) {
+      double best = 0.0;
+      for (int64_t j = 0; j < d; ++j) {
+        const double x = (double)(t[j] - t[0]) / (double)(t[d - 1] - t[0]);
+        const double y = (components(dist, k, t[j], group, stack) - g1) / (g0 - g1);
+        const double below = 1.0 - x - y; /* distance below the chord, up to a factor */
+        if (below > best) {
+          best = below;
+          *lambda = t[j];
+        }
+      }
+    }
+  }
+  free(t); free(group); free(stack);
   return 0;
 }

@@ -87,6 +87,38 @@ int mccref_consensus(const int64_t* row_ptr, const int32_t* col, int64_t n,
 /* Relabel cluster ids in [0, n) to [0, clusters) in order of first occurrence. */
 int mccref_canonicalize(const int32_t* in, int32_t* out, int64_t n, int32_t* clusters);
 
+/* ---- partition comparison (Results, "Evaluation metrics") ------------- */
+typedef struct {
+  int64_t mirkin;        /* ordered pairs co-clustered in exactly one of a, b */
+  int64_t split_join_ab; /* n - sum over clusters A of max_B |A n B| */
+  int64_t split_join_ba; /* n - sum over clusters B of max_A |A n B| */
+  int64_t split_join;    /* their sum: the split-join (projection) distance */
+  double rand;           /* Rand distance: mirkin / (n (n - 1)); 0 if n < 2 */
+  double vi;             /* variation of information, natural logarithm */
+  int32_t clusters_a, clusters_b;
+} mccref_comparison;
+
+int mccref_compare(const int32_t* a, const int32_t* b, int64_t n, mccref_comparison* r);
+
+/* dist[i * k + j] = split-join distance between partitions i and j (the
+ * edge weights of the grouping step, Methods, "Grouping homogeneous
+ * partitions").  labels as for mccref_consensus. */
+int mccref_split_join_matrix(const int32_t* labels, int32_t k, int64_t n, int64_t* dist);
+
+/* Groups of homogeneous partitions: i and j are linked when
+ * dist[i * k + j] <= lambda; the groups are the connected components,
+ * numbered 0, 1, ... in order of their smallest member. */
+int mccref_group(const int64_t* dist, int32_t k, int64_t lambda, int32_t* group,
+                 int32_t* ngroups);
+
+/* The threshold by the elbow rule: over the distinct pairwise distances t
+ * in increasing order, the number of groups g(t) falls; with both axes
+ * scaled to [0, 1] between the first and last point, the elbow is the t
+ * farthest below the straight line joining them (first such t on ties).
+ * Fewer than three distinct distances, or a flat curve: the smallest
+ * distance (0 when k < 2). */
+int mccref_elbow_lambda(const int64_t* dist, int32_t k, int64_t* lambda);
+
 #ifdef __cplusplus
 }
 #endif
