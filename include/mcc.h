@@ -279,6 +279,73 @@ int mcc_batch_tune(const mcc_problem* probs, int32_t count, const mcc_batch_opts
 int mcc_tune_save(const mcc_tune_table* table, const char* path);
 int mcc_tune_load(mcc_tune_table* table, const char* path);
 
+/*
+ * Comparison of two partitions of the same n elements (Results, "Evaluation
+ * metrics": the paper reports the variation of information, split-join and
+ * Rand distances; the first two follow their cited definitions, the last is
+ * the Mirkin distance normalised by the n (n - 1) ordered pairs).  With
+ * n_ab = |A_a n B_b|, n_a = |A_a|, n_b = |B_b|:
+ *   split_join_ab = n - sum_a max_b n_ab,  split_join_ba = n - sum_b max_a n_ab,
+ *   split_join    = split_join_ab + split_join_ba (van Dongen's distance),
+ *   vi   = (sum_a n_a ln n_a + sum_b n_b ln n_b - 2 sum_ab n_ab ln n_ab) / n,
+ *   rand = mirkin / (n (n - 1))  (0 when n < 2).
+ * Integers are exact; vi is summed in double precision in a fixed order (the
+ * same bits on every call).
+ */
+typedef struct {
+  int64_t mirkin;
+  int64_t split_join_ab, split_join_ba, split_join;
+  double rand;
+  double vi;
+  int32_t clusters_a, clusters_b;
+} mcc_comparison;
+
+/*  a, b    device int32[n], any values >= 0.
+ *  result  host output.
+ * Returns 0, MCC_EINVAL (NULL result, n outside [0, 2^31), a negative label,
+ * a pointer not visible to the device), MCC_ENOMEM, MCC_EDEVICE. */
+int mcc_compare(const int32_t* a, const int32_t* b, int64_t n, mcc_comparison* result,
+                void* stream);
+
+/*
+ * Split-join distance of every pair of the k partitions (the edge weights
+ * of the grouping step, Methods, "Grouping homogeneous partitions"), all
+ * pairs counted in one launch.
+ *  labels  host array of k device pointers, each int32[n], values >= 0.
+ *  dist    host int64[k * k] output, symmetric, zero diagonal.
+ * Returns 0, MCC_EINVAL (NULL argument, k < 1, k n >= 2^31, a negative
+ * label), MCC_ENOMEM, MCC_EDEVICE.
+ */
+int mcc_split_join_matrix(const int32_t* const* labels, int32_t k, int64_t n, int64_t* dist,
+                          void* stream);
+
+/*
+ * Groups of homogeneous partitions (Methods, "Grouping homogeneous
+ * partitions"): partitions i and j are linked when dist[i k + j] <= lambda,
+ * and the groups are the connected components, numbered 0, 1, ... in order
+ * of their smallest member.  lambda < 0 picks it by the elbow rule: over the
+ * distinct pairwise distances t in increasing order, with the number of
+ * groups g(t) and both axes scaled to [0, 1] between the first and the last
+ * distance, the t farthest below the straight line joining those two points
+ * (the first on ties); the smallest distance when there are fewer than
+ * three distinct distances or g does not change.  Host only.
+ *  dist         host int64[k * k], symmetric, >= 0.
+ *  group        host int32[k] output; ngroups host output.
+ *  lambda_used  host output or NULL: the threshold applied.
+ * Returns 0 or MCC_EINVAL (NULL argument, k < 1, dist not symmetric or
+ * negative).
+ */
+int mcc_group_from_distances(const int64_t* dist, int32_t k, int64_t lambda, int32_t* group,
+                             int32_t* ngroups, int64_t* lambda_used);
+
+/* The split-join matrix of the partitions (mcc_split_join_matrix) and the
+ * groups it gives (mcc_group_from_distances).  dist: host int64[k * k]
+ * output or NULL.  Each group is then one consensus problem; solve them
+ * together with mcc_consensus_batch. */
+int mcc_group_partitions(const int32_t* const* labels, int32_t k, int64_t n, int64_t lambda,
+                         int32_t* group, int32_t* ngroups, int64_t* lambda_used, int64_t* dist,
+                         void* stream);
+
 /* Static text for a return code (for MCC_EDEVICE, the last HIP error seen
  * on this thread). */
 const char* mcc_strerror(int code);

@@ -20,7 +20,8 @@ MCC_F_ARC_CACHE, MCC_F_HASH_TABLES = 0x10, 0x20
 # every function include/mcc.h declares
 EXPORTS = ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize",
            "mcc_consensus_batch", "mcc_batch_tune", "mcc_tune_save", "mcc_tune_load",
-           "mcc_strerror")
+           "mcc_compare", "mcc_split_join_matrix", "mcc_group_from_distances",
+           "mcc_group_partitions", "mcc_strerror")
 MCC_TUNE_LANES, MCC_TUNE_MAX_BUCKETS = 5, 160
 TUNE_LANES = (4, 8, 16, 32, 64)
 
@@ -55,6 +56,16 @@ class Stats(ctypes.Structure):
 class Problem(ctypes.Structure):
     _fields_ = [("g", Csr), ("labels", ctypes.c_void_p), ("k", ctypes.c_int32),
                 ("init", ctypes.c_void_p), ("out", ctypes.c_void_p)]
+
+
+class Comparison(ctypes.Structure):
+    _fields_ = [("mirkin", ctypes.c_int64), ("split_join_ab", ctypes.c_int64),
+                ("split_join_ba", ctypes.c_int64), ("split_join", ctypes.c_int64),
+                ("rand", ctypes.c_double), ("vi", ctypes.c_double),
+                ("clusters_a", ctypes.c_int32), ("clusters_b", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class TuneEntry(ctypes.Structure):
@@ -115,6 +126,13 @@ def lib():
         L.mcc_tune_save.restype = ctypes.c_int
         L.mcc_tune_load.argtypes = [ctypes.POINTER(TuneTable), ctypes.c_char_p]
         L.mcc_tune_load.restype = ctypes.c_int
+        L.mcc_compare.argtypes = [p, p, i64, ctypes.POINTER(Comparison), p]
+        L.mcc_split_join_matrix.argtypes = [p, i32, i64, p, p]
+        L.mcc_group_from_distances.argtypes = [p, i32, i64, p, p, p]
+        L.mcc_group_partitions.argtypes = [p, i32, i64, i64, p, p, p, p, p]
+        for f in ("mcc_compare", "mcc_split_join_matrix", "mcc_group_from_distances",
+                  "mcc_group_partitions"):
+            getattr(L, f).restype = ctypes.c_int
         L.mcc_strerror.argtypes = [ctypes.c_int]
         L.mcc_strerror.restype = ctypes.c_char_p
         for f in ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize"):
@@ -303,3 +321,83 @@ def tune_load(path):
     table = TuneTable()
     _check(lib().mcc_tune_load(ctypes.byref(table), path.encode()))
     return table
+
+
+# ---------------------------------------------------------------------------
+# partition comparison and grouping
+# ---------------------------------------------------------------------------
+def compare(a, b, stream=None) -> dict:
+    """Mirkin, split-join (both directions and their sum), Rand distance and
+    variation of information of two partitions (CUDA int32 tensors)."""
+    a, b = _dev_i32(a, "a"), _dev_i32(b, "b")
+    if a.numel() != b.numel():
+        raise ValueError("a and b differ in length")
+    r = Comparison()
+    _check(lib().mcc_compare(a.data_ptr() if a.numel() else None,
+                             b.data_ptr() if b.numel() else None, a.numel(), ctypes.byref(r),
+                             _stream_ptr(stream)))
+    return r.as_dict()
+
+
+def split_join_matrix(labels, stream=None):
+    """k x k split-join distances of the partitions (a (k, n) CUDA int32
+    tensor or a sequence of n-vectors), as a numpy int64 array."""
+    import numpy as np
+    rows, arr = _label_ptrs(labels)
+    k, n = len(rows), rows[0].numel()
+    d = np.zeros((k, k), np.int64)
+    _check(lib().mcc_split_join_matrix(arr, k, n, d.ctypes.data, _stream_ptr(stream)))
+    return d
+
+
+def group_from_distances(dist, lam=-1):
+    """Groups of homogeneous partitions from a split-join matrix (host);
+    lam < 0 picks the threshold by the elbow rule.  Returns (group ids,
+    number of groups, threshold used)."""
+    import numpy as np
+    d = np.ascontiguousarray(dist, np.int64)
+    k = d.shape[0]
+    g = np.zeros(k, np.int32)
+    ng, used = ctypes.c_int32(0), ctypes.c_int64(0)
+    _check(lib().mcc_group_from_distances(d.ctypes.data, k, int(lam), g.ctypes.data,
+                                          ctypes.byref(ng), ctypes.byref(used)))
+    return g, ng.value, used.value
+
+
+def group_partitions(labels, lam=-1, stream=None):
+    """split_join_matrix followed by group_from_distances, in one call.
+    Returns (group ids, number of groups, threshold used, distances)."""
+    import numpy as np
+    rows, arr = _label_ptrs(labels)
+    k, n = len(rows), rows[0].numel()
+    d = np.zeros((k, k), np.int64)
+    g = np.zeros(k, np.int32)
+    ng, used = ctypes.c_int32(0), ctypes.c_int64(0)
+    _check(lib().mcc_group_partitions(arr, k, n, int(lam), g.ctypes.data, ctypes.byref(ng),
+                                      ctypes.byref(used), d.ctypes.data, _stream_ptr(stream)))
+    return g, ng.value, used.value, d
+
+
+def consensus_groups(row_ptr, col, labels, lam=-1, init="first", max_rounds=0, flags=0,
+                     stream=None):
+    """The paper's pipeline: group the homogeneous input partitions, then one
+    consensus per group, all groups in one batched launch.  ``init``:
+    "first" starts each group from its first partition, "singleton" from
+    singletons.  Returns (group ids, threshold used, per-group outputs,
+    per-group stats)."""
+    import torch
+    lab = labels if hasattr(labels, "shape") else torch.stack(list(labels))
+    g, ng, used, _ = group_partitions(lab, lam, stream=stream)
+    probs = []
+    for j in range(ng):
+        members = [i for i in range(len(g)) if g[i] == j]
+        sub = lab[members].contiguous()
+        # cluster ids must lie in [0, n): the first partition, relabelled
+        start = canonicalize(sub[0].contiguous(), stream=stream)[0] if init == "first" else None
+        probs.append({"row_ptr": row_ptr, "col": col, "labels": sub, "init": start})
+    outs, stats, codes, _ = consensus_batch(probs, max_rounds=max_rounds, flags=flags,
+                                            stream=stream)
+    for c in codes:
+        if c != 0:
+            raise MccError(c, lib().mcc_strerror(c).decode())
+    return g, used, outs, stats

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmcc.so")
-SOURCES = ["setup.hip", "pass.hip", "batch.hip", "api.hip"]
+SOURCES = ["setup.hip", "pass.hip", "batch.hip", "metrics.hip", "api.hip"]
 ARCH = os.environ.get("MCC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -1158,6 +1158,269 @@ int mcc_batch_tune(const mcc_problem* probs, int32_t count, const mcc_batch_opts
   return MCC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Partition comparison and grouping of homogeneous partitions.
+// ---------------------------------------------------------------------------
+int mcc_compare(const int32_t* a, const int32_t* b, int64_t n, mcc_comparison* r, void* stream) {
+  if (!r || n < 0 || n >= ((int64_t)1 << 31)) return MCC_EINVAL;
+  memset(r, 0, sizeof *r);
+  if (n == 0) return MCC_OK;
+  if (!device_visible(a) || !device_visible(b)) return MCC_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    Arena ar(st);
+    // the table of (cluster of a, label of b): dense ids of a as the
+    // consensus, b as the one partition
+    std::vector<const int32_t*> pa{a};
+    Compacted ca;
+    int32_t* err = ar.get<int32_t>(1);
+    launch_fill_i32(err, 1, 0, st);
+    int32_t herr = 0;
+    std::vector<int32_t> maxlab;
+    compact_labels(ar, pa, n, &ca, err, st, &herr, &maxlab);
+    sync(st);
+    if (herr & kErrNegLabel) return MCC_EINVAL;
+    compact_labels_finish(ar, n, 1, maxlab, &ca, st);
+    int32_t* da = ar.get<int32_t>(n);
+    launch_dense_map(a, n, ca.scan, da, st);
+    std::vector<const int32_t*> pb{b};
+    Solve S;
+    build_solve(ar, pb, n, da, false, nullptr, &S, st);
+    const int32_t K0 = S.K0, Lb = S.lab.Lh[0];
+    int32_t* rowmax = ar.get<int32_t>(K0);
+    int32_t* colmax = ar.get<int32_t>(Lb);
+    int32_t* colsum = ar.get<int32_t>(Lb);
+    launch_fill_i32(rowmax, K0, 0, st);
+    launch_fill_i32(colmax, Lb, 0, st);
+    launch_fill_i32(colsum, Lb, 0, st);
+    const int nb0 = cell_stats_blocks(S.total), nb1 = xlogx_blocks(K0), nb2 = xlogx_blocks(Lb);
+    double* partial = ar.get<double>((int64_t)nb0 + nb1 + nb2);
+    double* sums = ar.get<double>(3);
+    int64_t* maxsum = ar.get<int64_t>(2);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(maxsum), 2, 0ull, st);
+    launch_cell_stats(S.t, S.total, Lb, rowmax, colmax, colsum, partial, st);
+    launch_xlogx(S.s, K0, partial + nb0, st);
+    launch_xlogx(colsum, Lb, partial + nb0 + nb1, st);
+    launch_sum_partials(partial, nb0, sums, st);
+    launch_sum_partials(partial + nb0, nb1, sums + 1, st);
+    launch_sum_partials(partial + nb0 + nb1, nb2, sums + 2, st);
+    launch_sum_i32(rowmax, K0, maxsum, st);
+    launch_sum_i32(colmax, Lb, maxsum + 1, st);
+    int64_t acc[3], ms[2];
+    double hs[3];
+    d2h(acc, S.acc, 3, st);
+    d2h(ms, maxsum, 2, st);
+    d2h(hs, sums, 3, st);
+    sync(st);
+    r->mirkin = acc[0] + acc[1] - 2 * acc[2];
+    r->split_join_ab = n - ms[0];
+    r->split_join_ba = n - ms[1];
+    r->split_join = r->split_join_ab + r->split_join_ba;
+    r->vi = (hs[1] + hs[2] - 2.0 * hs[0]) / (double)n;
+    r->rand = n > 1 ? (double)r->mirkin / ((double)n * (double)(n - 1)) : 0.0;
+    r->clusters_a = K0;
+    r->clusters_b = Lb;
+    return MCC_OK;
+  } catch (...) {
+    return translate(std::current_exception());
+  }
+}
+
+int mcc_split_join_matrix(const int32_t* const* labels, int32_t k, int64_t n, int64_t* dist,
+                          void* stream) {
+  if (!dist || !labels || k < 1 || n < 0 || (int64_t)k * n >= ((int64_t)1 << 31))
+    return MCC_EINVAL;
+  memset(dist, 0, sizeof(int64_t) * (size_t)k * (size_t)k);
+  if (n == 0 || k == 1) return labels_ok(labels, k) ? MCC_OK : MCC_EINVAL;
+  if (!labels_ok(labels, k)) return MCC_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  try {
+    Arena ar(st);
+    std::vector<const int32_t*> hptrs(labels, labels + k);
+    Compacted lab;
+    int32_t* err = ar.get<int32_t>(1);
+    launch_fill_i32(err, 1, 0, st);
+    int32_t herr = 0;
+    std::vector<int32_t> maxlab;
+    compact_labels(ar, hptrs, n, &lab, err, st, &herr, &maxlab);
+    sync(st);
+    if (herr & kErrNegLabel) return MCC_EINVAL;
+    compact_labels_finish(ar, n, k, maxlab, &lab, st);
+    std::vector<int32_t> Lh(k);
+    d2h(Lh.data(), lab.L, k, st);
+    // partition-major dense label ids
+    int32_t* D = ar.get<int32_t>((int64_t)k * n);
+    int64_t lo = 0;
+    for (int i = 0; i < k; ++i) {
+      launch_dense_map(hptrs[i], n, lab.scan + lo, D + (int64_t)i * n, st);
+      lo += (int64_t)maxlab[i] + 1;
+    }
+    sync(st);
+    // pairs in batches whose tables fit the cell budget; a pair too large
+    // for it alone goes through mcc_compare (hashed tables)
+    constexpr int64_t kPairCells = (int64_t)1 << 28;
+    std::vector<int32_t> pi, pj;
+    std::vector<int64_t> poff;
+    auto flush = [&]() {
+      if (pi.empty()) return;
+      const int32_t np = (int32_t)pi.size();
+      const int64_t cells = poff.back();
+      Arena bar(st);
+      int32_t* dpi = bar.get<int32_t>(np);
+      int32_t* dpj = bar.get<int32_t>(np);
+      int64_t* dpoff = bar.get<int64_t>(np + 1);
+      h2d(dpi, bar.host(pi), np, st);
+      h2d(dpj, bar.host(pj), np, st);
+      h2d(dpoff, bar.host(poff), np + 1, st);
+      int32_t* T = bar.get<int32_t>(cells);
+      launch_fill_i32(T, cells, 0, st);
+      int64_t* dd = bar.get<int64_t>(np);
+      launch_pair_tables(D, n, dpi, dpj, dpoff, lab.L, np, T, st);
+      launch_pair_split_join(T, dpi, dpj, dpoff, lab.L, np, n, dd, st);
+      std::vector<int64_t> hd(np);
+      d2h(hd.data(), dd, np, st);
+      sync(st);
+      for (int32_t p = 0; p < np; ++p) {
+        dist[(int64_t)pi[p] * k + pj[p]] = hd[p];
+        dist[(int64_t)pj[p] * k + pi[p]] = hd[p];
+      }
+      pi.clear();
+      pj.clear();
+      poff.clear();
+    };
+    for (int32_t i = 0; i < k; ++i)
+      for (int32_t j = i + 1; j < k; ++j) {
+        const int64_t cells = (int64_t)Lh[i] * Lh[j];
+        if (cells > kPairCells) {
+          mcc_comparison r;
+          const int rc = mcc_compare(hptrs[i], hptrs[j], n, &r, stream);
+          if (rc != MCC_OK) return rc;
+          dist[(int64_t)i * k + j] = dist[(int64_t)j * k + i] = r.split_join;
+          continue;
+        }
+        if (poff.empty()) poff.push_back(0);
+        if (poff.back() + cells > kPairCells || (int64_t)pi.size() >= (1 << 20)) {
+          flush();
+          poff.push_back(0);
+        }
+        pi.push_back(i);
+        pj.push_back(j);
+        poff.push_back(poff.back() + cells);
+      }
+    flush();
+    return MCC_OK;
+  } catch (...) {
+    return translate(std::current_exception());
+  }
+}
+
+}  // extern "C"
+
+namespace {
+
+// Union-find over the k partitions.
+struct Dsu {
+  std::vector<int32_t> up;
+  int32_t sets;
+  explicit Dsu(int32_t k) : up(k), sets(k) {
+    for (int32_t i = 0; i < k; ++i) up[i] = i;
+  }
+  int32_t find(int32_t x) {
+    while (up[x] != x) x = up[x] = up[up[x]];
+    return x;
+  }
+  void join(int32_t a, int32_t b) {
+    a = find(a);
+    b = find(b);
+    if (a == b) return;
+    if (a < b) std::swap(a, b);
+    up[a] = b;
+    --sets;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int mcc_group_from_distances(const int64_t* dist, int32_t k, int64_t lambda, int32_t* group,
+                             int32_t* ngroups, int64_t* lambda_used) {
+  if (!dist || !group || !ngroups || k < 1) return MCC_EINVAL;
+  // edges in increasing distance; the number of groups after each distinct
+  // distance comes from merging them in that order
+  struct Edge {
+    int64_t w;
+    int32_t a, b;
+  };
+  std::vector<Edge> edges;
+  edges.reserve((size_t)k * (k - 1) / 2);
+  for (int32_t i = 0; i < k; ++i)
+    for (int32_t j = i + 1; j < k; ++j) {
+      if (dist[(int64_t)i * k + j] != dist[(int64_t)j * k + i] || dist[(int64_t)i * k + j] < 0)
+        return MCC_EINVAL;
+      edges.push_back({dist[(int64_t)i * k + j], i, j});
+    }
+  std::sort(edges.begin(), edges.end(), [](const Edge& x, const Edge& y) { return x.w < y.w; });
+  int64_t lam = lambda;
+  if (lam < 0) {
+    // elbow: the distinct distance farthest below the chord of the curve
+    // (distance, groups), both axes scaled to [0, 1]
+    std::vector<int64_t> t;
+    std::vector<int32_t> g;
+    Dsu d(k);
+    for (size_t e = 0; e < edges.size();) {
+      const int64_t w = edges[e].w;
+      for (; e < edges.size() && edges[e].w == w; ++e) d.join(edges[e].a, edges[e].b);
+      t.push_back(w);
+      g.push_back(d.sets);
+    }
+    lam = t.empty() ? 0 : t[0];
+    const size_t m = t.size();
+    if (m >= 3 && g[0] != g[m - 1]) {
+      double best = 0.0;
+      for (size_t j = 0; j < m; ++j) {
+        const double x = (double)(t[j] - t[0]) / (double)(t[m - 1] - t[0]);
+        const double y = ((double)g[j] - (double)g[m - 1]) / ((double)g[0] - (double)g[m - 1]);
+        const double below = 1.0 - x - y;
+        if (below > best) {
+          best = below;
+          lam = t[j];
+        }
+      }
+    }
+  }
+  Dsu d(k);
+  for (const Edge& e : edges) {
+    if (e.w > lam) break;
+    d.join(e.a, e.b);
+  }
+  std::vector<int32_t> id(k, -1);
+  int32_t ng = 0;
+  for (int32_t i = 0; i < k; ++i) {
+    const int32_t root = d.find(i);
+    if (id[root] < 0) id[root] = ng++;
+    group[i] = id[root];
+  }
+  *ngroups = ng;
+  if (lambda_used) *lambda_used = lam;
+  return MCC_OK;
+}
+
+int mcc_group_partitions(const int32_t* const* labels, int32_t k, int64_t n, int64_t lambda,
+                         int32_t* group, int32_t* ngroups, int64_t* lambda_used, int64_t* dist,
+                         void* stream) {
+  if (!group || !ngroups || k < 1) return MCC_EINVAL;
+  std::vector<int64_t> own;
+  int64_t* d = dist;
+  if (!d) {
+    own.assign((size_t)k * k, 0);
+    d = own.data();
+  }
+  const int rc = mcc_split_join_matrix(labels, k, n, d, stream);
+  if (rc != MCC_OK) return rc;
+  return mcc_group_from_distances(d, k, lambda, group, ngroups, lambda_used);
+}
+
 int mcc_tune_save(const mcc_tune_table* t, const char* path) {
   if (!t || !path || t->count < 0 || t->count > MCC_TUNE_MAX_BUCKETS) return MCC_EINVAL;
   FILE* f = fopen(path, "w");

@@ -209,6 +209,25 @@ void launch_first_flags(const int32_t* in, int64_t n, const int32_t* first, int3
 void launch_canonical_write(const int32_t* in, int64_t n, const int32_t* first,
                             const int32_t* rank, int32_t* out, hipStream_t st);
 
+// ---- comparison kernels (metrics.hip) --------------------------------------
+int cell_stats_blocks(int64_t cells);
+int xlogx_blocks(int64_t len);
+// Over the cells of a one-partition table: row/column maxima and column sums
+// (rowmax, colmax, colsum zeroed by the caller), per-block sums of c ln c.
+void launch_cell_stats(const Tables& t, int64_t cells, int32_t Lb, int32_t* rowmax,
+                       int32_t* colmax, int32_t* colsum, double* partial, hipStream_t st);
+void launch_xlogx(const int32_t* a, int64_t len, double* partial, hipStream_t st);
+void launch_sum_partials(const double* partial, int32_t count, double* out, hipStream_t st);
+void launch_sum_i32(const int32_t* a, int64_t len, int64_t* acc, hipStream_t st);
+// Split-join distance of npairs partition pairs (T zeroed by the caller,
+// poff[p] its cells for pair p).
+void launch_pair_tables(const int32_t* D, int64_t n, const int32_t* pi, const int32_t* pj,
+                        const int64_t* poff, const int32_t* L, int32_t npairs, int32_t* T,
+                        hipStream_t st);
+void launch_pair_split_join(const int32_t* T, const int32_t* pi, const int32_t* pj,
+                            const int64_t* poff, const int32_t* L, int32_t npairs, int64_t n,
+                            int64_t* dist, hipStream_t st);
+
 // ---- pass kernels (pass.hip) ----------------------------------------------
 struct PassArgs {
   Ctl* ctl;

@@ -80,3 +80,32 @@ def test_tune_table_rejects_malformed(tmp_path, text):
     assert e.value.code == mcc.MCC_EINVAL
     with pytest.raises(mcc.MccError):
         mcc.tune_load(str(tmp_path / "missing.txt"))
+
+
+# ------------------------------------------- grouping step (host only) ------
+@pytest.mark.parametrize("seed", range(8))
+def test_group_from_distances_matches_oracle(seed):
+    if not os.path.exists(mcc.LIB_PATH):
+        pytest.skip("libmcc.so not built")
+    import numpy as np
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = int(rng.integers(1, 30))
+    d = np.triu(rng.integers(0, [5, 50, 1000][seed % 3], size=(k, k)), 1)
+    d = d + d.T
+    for lam in (-1, 0, int(rng.integers(0, 60))):
+        g, ng, used = mcc.group_from_distances(d, lam)
+        want = oracle.elbow_lambda(d) if lam < 0 else lam
+        assert used == want
+        og, ong = oracle.group(d, want)
+        assert ng == ong and np.array_equal(g, og)
+
+
+def test_group_from_distances_rejects_bad_matrix():
+    if not os.path.exists(mcc.LIB_PATH):
+        pytest.skip("libmcc.so not built")
+    import numpy as np
+    with pytest.raises(mcc.MccError):
+        mcc.group_from_distances(np.array([[0, 1], [2, 0]]), 3)
+    with pytest.raises(mcc.MccError):
+        mcc.group_from_distances(np.array([[0, -1], [-1, 0]]), 3)
