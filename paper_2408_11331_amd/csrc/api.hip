@@ -524,7 +524,16 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
     a.in_ptr = in_ptr;
     a.in_pos = in_pos;
     a.cells = S.total;
+    a.nnz = nnz;
+    a.arcs_aligned = ((uintptr_t)g->col & 15) == 0 ? 1 : 0;  // ac comes from the arena (aligned)
     a.hflag = S.t.hashed ? ar.get<int32_t>(1) : nullptr;
+    a.K0 = S.K0;
+    if (S.t.hashed) {
+      a.mstart = ar.get<int32_t>((int64_t)S.K0 + 1);
+      a.mcnt = ar.get<int32_t>(S.K0);
+      a.members = ar.get<int32_t>(n);
+      a.mscan_tmp = ar.get<int32_t>(scan_tmp_elems(S.K0));
+    }
     a.cn_bytes = S.K0 <= 256 ? 1 : (S.K0 <= 65536 ? 2 : 4);
     if (a.cn_bytes == 4) {
       a.Cn = S.C;

@@ -102,10 +102,12 @@ __device__ inline int32_t hget(const Tables& t, uint64_t key) {
   return 0;
 }
 
-// Slot of `key`, claimed if absent.  The table is sized and rebuilt so that
-// it is never more than half full; should no slot be found, *herr is set
-// (the solve then reports an error) and slot 0 is returned.
-__device__ inline uint32_t hslot(const Tables& t, uint64_t key) {
+// Slot of `key`, claimed if absent (then `claimed` is incremented: callers
+// add their claims to *hocc once per wave, flush_claims).  The table is
+// sized and rebuilt so that it is never more than half full; should no slot
+// be found, *herr is set (the solve then reports an error) and slot 0 is
+// returned.
+__device__ inline uint32_t hslot(const Tables& t, uint64_t key, int32_t& claimed) {
   unsigned long long* H = reinterpret_cast<unsigned long long*>(t.N);
   uint64_t h = hstart(t, key);
   for (uint64_t q = 0; q <= t.hmask; ++q) {
@@ -115,7 +117,7 @@ __device__ inline uint32_t hslot(const Tables& t, uint64_t key) {
       const uint64_t prev = atomicCAS(&H[2 * h], (unsigned long long)kHashEmpty,
                                       (unsigned long long)key);
       if (prev == kHashEmpty) {
-        atomicAdd(t.hocc, 1);
+        ++claimed;
         return (uint32_t)h;
       }
       if (prev == key) return (uint32_t)h;
@@ -133,8 +135,17 @@ __device__ inline int32_t* counter(const Tables& t, uint32_t c) {
 
 // Cell of (i, x, l) for an update: the dense position, or the key's slot
 // (claimed if new).
-__device__ inline uint32_t cell_upd(const Tables& t, int i, int32_t x, int32_t l) {
-  return t.hashed ? hslot(t, hkey(t, i, x, l)) : cell(t, i, x, l);
+__device__ inline uint32_t cell_upd(const Tables& t, int i, int32_t x, int32_t l,
+                                    int32_t& claimed) {
+  return t.hashed ? hslot(t, hkey(t, i, x, l), claimed) : cell(t, i, x, l);
+}
+
+// Add the wave's claimed slots to the occupancy counter (all lanes of the
+// wave call it).
+__device__ inline void flush_claims(const Tables& t, int32_t claimed) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) claimed += __shfl_xor(claimed, o, 64);
+  if ((threadIdx.x & 63) == 0 && claimed) atomicAdd(t.hocc, claimed);
 }
 
 // Count of (i, x, l) for scoring.
@@ -253,11 +264,22 @@ struct PassArgs {
   const int32_t* in_pos;
   int64_t cells;      // table cells (keys >= cells address cluster sizes)
   int32_t* hflag;     // hashed tables: 1 while the current pass rebuilds them
+  // Hashed tables: member lists of the clusters as they stand at the start of
+  // the pass (members[mstart[x] .. mstart[x + 1]) are the vertices of x), so
+  // that a small cluster's agreement sum is taken over its members' label
+  // rows instead of k table probes.  Null otherwise.
+  int32_t* mstart;    // K0 + 1
+  int32_t* mcnt;      // K0 (fill cursors)
+  int32_t* members;   // n
+  int32_t* mscan_tmp;
+  int32_t K0;
   // Narrow copy of C (uint8 when K0 <= 256, uint16 when K0 <= 65536, else
   // C itself) for the per-arc cluster gathers: a few MiB stay resident in
   // every XCD's L2 where the int32 array would not.
   void* Cn;
   int32_t cn_bytes;
+  int32_t arcs_aligned;  // col (and ac) start on a 16-byte boundary
+  int64_t nnz;
 };
 
 // Compile-time variants: CN is the narrow copy's width in bytes (0: read the
@@ -269,6 +291,11 @@ __device__ inline int32_t cn_load_t(const PassArgs& a, int64_t j, int32_t u) {
   if (CN == 2) return ((const uint16_t*)a.Cn)[u];
   return ((const int32_t*)a.Cn)[u];
 }
+
+// Largest cluster whose agreement sum is taken over its members' label rows
+// when the table is hashed: s rows of 4k bytes streamed against k random
+// probes of a table in HBM.
+constexpr int32_t kMemberSumMax = 16;
 
 // Table layouts as compile-time variants.
 enum TableKind { kBlocked = 0, kInterleaved = 1, kHashed = 2 };

@@ -140,7 +140,27 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
     // S_y(v) summed over the group's lanes
     auto agree = [&](int32_t y) -> int32_t {
       int32_t sum = 0;
-      if (a.t.hashed) {
+      if (a.members && a.s[y] <= kMemberSumMax) {
+        // S_y(v) = sum over members u of y of the partitions agreeing on u, v;
+        // the member ids are read once, one per lane, and broadcast
+        const int32_t cnt = a.s[y], b = a.mstart[y];
+        for (int32_t m0 = 0; m0 < cnt; m0 += G) {
+          const int32_t mid = m0 + lane < cnt ? a.members[b + m0 + lane] : 0;
+          const int32_t mc = min(G, cnt - m0);
+          for (int32_t j = 0; j < mc; ++j) {
+          const int32_t* ru = a.Lvm + (int64_t)__shfl(mid, j, G) * k;
+          if (kfits) {
+#pragma unroll
+            for (int t = 0; t < KR; ++t) {
+              int i = lane + t * G;
+              if (i < k) sum += ru[i] == lab[t];
+            }
+          } else {
+            for (int i = lane; i < k; i += G) sum += ru[i] == row[i];
+          }
+          }
+        }
+      } else if (a.t.hashed) {
         const uint64_t ky = (uint64_t)(uint32_t)y << 32;
         if (kfits) {  // implies lds_geom
 #pragma unroll
@@ -242,11 +262,12 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
 //     inserts the key (tail, head cluster) into a tile-wide LDS hash set and
 //     the first insertion of a key counts a candidate for the tail (a
 //     self-loop points at the own cluster and drops out with it);
-//  3. the set is compacted into per-vertex runs of candidate clusters;
-//  4. the pairs (candidate cluster, vertex) and (own cluster, boundary
-//     vertex) form a flat list that groups of kProbeLanes lanes probe,
-//     lanes spread over the partitions, with the next batch's label rows in
-//     flight while the current batch probes;
+//  3. the set is compacted into one run of pairs per boundary vertex, its
+//     own cluster first, then its candidate clusters;
+//  4. groups of kProbeLanes lanes probe the flat list of pairs, lanes spread
+//     over the partitions, with the next batch's label rows in flight while
+//     the current batch probes (consecutive pairs of one vertex share one
+//     load of its label row);
 //  5. one thread per vertex takes the smallest (gain, cluster id).
 // A vertex whose key finds no slot in the set is deferred to a list that
 // the group scorer finishes in the same pass, so results never depend on
@@ -259,6 +280,7 @@ constexpr int kPairMax = kSetSlots + kBlock;  // every candidate plus one own pa
 constexpr int kProbeLanes = 16;
 constexpr int kProbeRegs = 64 / kProbeLanes;  // labels per lane when k <= 64
 constexpr int kProbeBatch = 4;
+static_assert(kMemberSumMax <= kProbeLanes, "member ids of a small cluster fit one probe group");
 
 template <int CN, int TK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
@@ -268,11 +290,10 @@ void k_score_tile(PassArgs a) {
   __shared__ int32_t s_c[kBlock];
   __shared__ int32_t s_nc[kBlock];    // candidates of each vertex
   __shared__ int32_t s_def[kBlock];   // 1: vertex deferred to the group scorer
-  __shared__ int32_t s_cur[kBlock];   // fill cursor, then start of the vertex's run
-  __shared__ int32_t s_bv[kBlock];    // boundary vertices of the tile
+  __shared__ int32_t s_cur[kBlock];   // fill cursor of the vertex's run
   __shared__ int32_t s_set[kSetSlots];
-  __shared__ int32_t s_cl[kSetSlots];  // candidate keys grouped by vertex
-  __shared__ int32_t s_S[kPairMax];    // agreement sums: candidates, then own clusters
+  __shared__ int32_t s_cl[kPairMax];   // pair keys (vertex << 24 | cluster), run per vertex
+  __shared__ int32_t s_S[kPairMax];    // agreement sum of each pair
   const int t = threadIdx.x;
   const int32_t k = a.k;
   const bool kfits = k <= kProbeRegs * kProbeLanes;
@@ -291,25 +312,48 @@ void k_score_tile(PassArgs a) {
     for (int j = t; j < kSetSlots; j += kBlock) s_set[j] = -1;
     __syncthreads();
     const int32_t A = s_off[nv];
-    // each thread takes U consecutive arcs of every chunk: one search for
-    // the tail of the first, then a walk along the row offsets
-    const int32_t* colp = a.col + a0;
-    for (int32_t cb = 0; cb < A; cb += kArcChunk) {
-      constexpr int U = kArcChunk / kBlock;
-      const int32_t jt = cb + t * U;
+    // each thread takes U consecutive arcs of every chunk, read as one
+    // 16-byte load from an aligned arc index (the tile's arcs are walked from
+    // the aligned index at or before its first arc): one search for the tail
+    // of the first, then a walk along the row offsets
+    constexpr int U = kArcChunk / kBlock;
+    static_assert(U == 4, "one int4 load per thread and chunk");
+    const int32_t sh = a.arcs_aligned ? (int32_t)(a0 & 3) : 0;
+    const int64_t base = a0 - sh;
+    const int32_t* src = CN ? a.col : a.ac;  // heads, or the per-arc clusters
+    for (int32_t cb = 0; cb < A + sh; cb += kArcChunk) {
+      const int32_t jt = cb + t * U - sh;  // tile-relative index of the thread's first arc
+      int32_t hd[U];
+      if (jt + U > 0 && jt < A) {
+        const int64_t gi = base + cb + t * U;
+        if (a.arcs_aligned && gi + U <= a.nnz) {
+          const int4 q4 = *reinterpret_cast<const int4*>(src + gi);
+          hd[0] = q4.x;
+          hd[1] = q4.y;
+          hd[2] = q4.z;
+          hd[3] = q4.w;
+        } else {
+#pragma unroll
+          for (int r = 0; r < U; ++r) {
+            const int32_t j = jt + r;
+            hd[r] = (j >= 0 && j < A) ? src[a0 + j] : 0;
+          }
+        }
+      }
       int32_t cu[U];
 #pragma unroll
       for (int r = 0; r < U; ++r) {
         const int32_t j = jt + r;
         cu[r] = -1;
-        if (j < A) cu[r] = cn_load_t<CN>(a, a0 + j, CN ? colp[j] : 0);
+        if (j >= 0 && j < A) cu[r] = CN ? cn_load_t<CN>(a, 0, hd[r]) : hd[r];
       }
       int lo = 0;
-      if (jt < A) {
-        int hi = nv - 1;  // tail: the last vertex whose row starts at or before jt
+      const int32_t j0 = max(jt, 0);
+      if (j0 < A) {
+        int hi = nv - 1;  // tail: the last vertex whose row starts at or before j0
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
-          if (s_off[mid] <= jt) lo = mid;
+          if (s_off[mid] <= j0) lo = mid;
           else hi = mid - 1;
         }
       }
@@ -317,7 +361,7 @@ void k_score_tile(PassArgs a) {
 #pragma unroll
       for (int r = 0; r < U; ++r) {
         const int32_t j = jt + r;
-        if (j >= A) continue;
+        if (j < 0 || j >= A) continue;
         while (s_off[lo + 1] <= j) ++lo;
         const int32_t x = cu[r];
         if (x == s_c[lo]) continue;
@@ -361,12 +405,11 @@ void k_score_tile(PassArgs a) {
         boundary += 1;
       }
     }
-    int32_t tot;
-    const int32_t sc0 = block_exclusive_scan(is_b ? (nc << 16) | 1 : 0, &tot);
-    const int32_t ncand = tot >> 16, nb = tot & 0xffff;
-    const int32_t coff = sc0 >> 16;
-    s_cur[t] = coff;
-    if (is_b) s_bv[sc0 & 0xffff] = t;
+    // one run per boundary vertex: its own cluster, then its candidates
+    int32_t npairs;
+    const int32_t coff = block_exclusive_scan(is_b ? nc + 1 : 0, &npairs);
+    s_cur[t] = coff + 1;
+    if (is_b) s_cl[coff] = (t << 24) | s_c[t];
     __syncthreads();
     for (int h = t; h < kSetSlots; h += kBlock) {
       const int32_t key = s_set[h];
@@ -376,59 +419,69 @@ void k_score_tile(PassArgs a) {
       s_cl[atomicAdd(&s_cur[tv], 1)] = key;
     }
     __syncthreads();
-    // probes over the pairs: p < ncand candidate pairs, then one own pair
-    // per boundary vertex
-    const int npairs = ncand + nb;
     constexpr int kStride = (kBlock / kProbeLanes) * kProbeBatch;
     auto pair_at = [&](int p, int32_t& x, uint32_t& row) {
       x = -1;
       row = 0;
       if (p < npairs) {
-        int tv;
-        if (p < ncand) {
-          const int32_t key = s_cl[p];
-          tv = (int)((uint32_t)key >> 24);
-          x = key & 0xffffff;
-        } else {
-          tv = s_bv[p - ncand];
-          x = s_c[tv];
-        }
-        row = (uint32_t)(v0 + tv) * (uint32_t)k;
+        const int32_t key = s_cl[p];
+        x = key & 0xffffff;
+        row = (uint32_t)(v0 + (int)((uint32_t)key >> 24)) * (uint32_t)k;
       }
+    };
+    // label rows of a batch; a pair of the same vertex as the one before it
+    // takes that pair's registers instead of loading again
+    auto load_rows = [&](const int32_t* xq, const uint32_t* vq, int32_t (*lq)[kProbeRegs]) {
+#pragma unroll
+      for (int q = 0; q < kProbeBatch; ++q) {
+        const bool same = q > 0 && xq[q - 1] >= 0 && vq[q] == vq[q - 1];
+#pragma unroll
+        for (int r = 0; r < kProbeRegs; ++r) {
+          const int i = lane + r * kProbeLanes;
+          lq[q][r] = (xq[q] >= 0 && i < k && !same) ? a.Lvm[vq[q] + i] : 0;
+        }
+      }
+#pragma unroll
+      for (int q = 1; q < kProbeBatch; ++q)
+        if (xq[q - 1] >= 0 && vq[q] == vq[q - 1]) {
+#pragma unroll
+          for (int r = 0; r < kProbeRegs; ++r) lq[q][r] = lq[q - 1][r];
+        }
     };
     if (kfits) {
       int32_t xs[kProbeBatch], lab[kProbeBatch][kProbeRegs];
       uint32_t vs[kProbeBatch];
       int p0 = g * kProbeBatch;
 #pragma unroll
-      for (int q = 0; q < kProbeBatch; ++q) {
-        pair_at(p0 + q, xs[q], vs[q]);
-#pragma unroll
-        for (int r = 0; r < kProbeRegs; ++r) {
-          const int i = lane + r * kProbeLanes;
-          lab[q][r] = (xs[q] >= 0 && i < k) ? a.Lvm[vs[q] + i] : 0;
-        }
-      }
+      for (int q = 0; q < kProbeBatch; ++q) pair_at(p0 + q, xs[q], vs[q]);
+      load_rows(xs, vs, lab);
       for (; p0 < npairs; p0 += kStride) {
         int32_t xn[kProbeBatch], labn[kProbeBatch][kProbeRegs];
         uint32_t vn[kProbeBatch];
 #pragma unroll
-        for (int q = 0; q < kProbeBatch; ++q) {
-          pair_at(p0 + kStride + q, xn[q], vn[q]);
-#pragma unroll
-          for (int r = 0; r < kProbeRegs; ++r) {
-            const int i = lane + r * kProbeLanes;
-            labn[q][r] = (xn[q] >= 0 && i < k) ? a.Lvm[vn[q] + i] : 0;
-          }
-        }
+        for (int q = 0; q < kProbeBatch; ++q) pair_at(p0 + kStride + q, xn[q], vn[q]);
+        load_rows(xn, vn, labn);
         int32_t sums[kProbeBatch];
 #pragma unroll
         for (int q = 0; q < kProbeBatch; ++q) {
           int32_t sum = 0;
+          if (TK == kHashed && xs[q] >= 0 && a.members && a.s[xs[q]] <= kMemberSumMax) {
+            const int32_t cnt = a.s[xs[q]];  // <= kProbeLanes: one member id per lane
+            const int32_t mid = lane < cnt ? a.members[a.mstart[xs[q]] + lane] : 0;
+            for (int32_t m = 0; m < cnt; ++m) {
+              const uint32_t ru = (uint32_t)__shfl(mid, m, kProbeLanes) * (uint32_t)k;
 #pragma unroll
-          for (int r = 0; r < kProbeRegs; ++r) {
-            const int i = lane + r * kProbeLanes;
-            if (xs[q] >= 0 && i < k) sum += count_t<TK>(a.t, i, xs[q], lab[q][r]);
+              for (int r = 0; r < kProbeRegs; ++r) {
+                const int i = lane + r * kProbeLanes;
+                if (i < k) sum += a.Lvm[ru + i] == lab[q][r];
+              }
+            }
+          } else {
+#pragma unroll
+            for (int r = 0; r < kProbeRegs; ++r) {
+              const int i = lane + r * kProbeLanes;
+              if (xs[q] >= 0 && i < k) sum += count_t<TK>(a.t, i, xs[q], lab[q][r]);
+            }
           }
           sums[q] = sum;
         }
@@ -455,7 +508,16 @@ void k_score_tile(PassArgs a) {
           int32_t sum = 0;
           if (x >= 0) {
             const int32_t* row = a.Lvm + ro;
-            for (int i = lane; i < k; i += kProbeLanes) sum += count_t<TK>(a.t, i, x, row[i]);
+            if (TK == kHashed && a.members && a.s[x] <= kMemberSumMax) {
+              const int32_t cnt = a.s[x];
+              const int32_t mid = lane < cnt ? a.members[a.mstart[x] + lane] : 0;
+              for (int32_t m = 0; m < cnt; ++m) {
+                const int32_t* ru = a.Lvm + (int64_t)__shfl(mid, m, kProbeLanes) * k;
+                for (int i = lane; i < k; i += kProbeLanes) sum += ru[i] == row[i];
+              }
+            } else {
+              for (int i = lane; i < k; i += kProbeLanes) sum += count_t<TK>(a.t, i, x, row[i]);
+            }
           }
           const int32_t sq = group_sum<kProbeLanes>(sum);
           if (lane == 0 && x >= 0) s_S[p0 + q] = sq;
@@ -466,11 +528,11 @@ void k_score_tile(PassArgs a) {
     if (is_b) {
       const int64_t v = v0 + t;
       const int32_t c = s_c[t];
-      const int64_t s_own = s_S[ncand + (sc0 & 0xffff)];
+      const int64_t s_own = s_S[coff];
       const int64_t scz = a.s[c];
       int64_t bestd = 0;
       int32_t bestx = kNone;
-      for (int j = coff; j < coff + nc; ++j) {
+      for (int j = coff + 1; j <= coff + nc; ++j) {
         const int32_t x = s_cl[j] & 0xffffff;
         int64_t d = 2 * (s_own - (int64_t)s_S[j]) + (int64_t)k * ((int64_t)a.s[x] - scz - 1);
         if (a.literal) d += k;
@@ -523,12 +585,14 @@ __device__ inline int64_t move_counts(const PassArgs& a, int64_t v, int32_t from
                                       int32_t d, int lane, int64_t* ds2) {
   int64_t acc = 0;
   const int32_t* row = a.Lvm + v * a.k;
+  int32_t claimed = 0;  // these keys exist already (k_apply_all added them)
   for (int i = lane; i < a.k; i += 64) {
     const int32_t l = row[i];
-    int32_t o1 = atomicAdd(counter(a.t, cell_upd(a.t, i, to, l)), d);
-    int32_t o2 = atomicAdd(counter(a.t, cell_upd(a.t, i, from, l)), -d);
+    int32_t o1 = atomicAdd(counter(a.t, cell_upd(a.t, i, to, l, claimed)), d);
+    int32_t o2 = atomicAdd(counter(a.t, cell_upd(a.t, i, from, l, claimed)), -d);
     acc += 2 * (int64_t)o1 * d + 1 - 2 * (int64_t)o2 * d + 1;
   }
+  if (claimed) atomicAdd(a.t.hocc, claimed);
   if (lane == 0) {
     int32_t o1 = atomicAdd(&a.s[to], d);
     int32_t o2 = atomicAdd(&a.s[from], -d);
@@ -588,6 +652,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 64;
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) / 64;
   int64_t dn2 = 0, ds2 = 0;
+  int32_t claimed = 0;
   for (int64_t v0 = wave * 64; v0 < a.n; v0 += nwaves * 64) {
     const int64_t v = v0 + lane;
     const int32_t p = v < a.n ? a.prop[v] : kNone;
@@ -601,8 +666,8 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
       const int32_t* row = a.Lvm + w * a.k;
       for (int i = lane; i < a.k; i += 64) {
         const int32_t l = row[i];
-        agg_add(hkey, hval, a, cell_upd(a.t, i, to, l), +1, &dn2, &ds2);
-        agg_add(hkey, hval, a, cell_upd(a.t, i, from, l), -1, &dn2, &ds2);
+        agg_add(hkey, hval, a, cell_upd(a.t, i, to, l, claimed), +1, &dn2, &ds2);
+        agg_add(hkey, hval, a, cell_upd(a.t, i, from, l, claimed), -1, &dn2, &ds2);
       }
       if (lane == 0) {
         agg_add(hkey, hval, a, a.cells + to, +1, &dn2, &ds2);
@@ -622,6 +687,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
       ds2 += 2 * (int64_t)old * d + (int64_t)d * d;
     }
   }
+  if (a.t.hashed) flush_claims(a.t, claimed);
   dn2 = wave_sum64(dn2);
   ds2 = wave_sum64(ds2);
   if (lane == 0) {
@@ -746,11 +812,25 @@ __global__ __launch_bounds__(kBlock) void k_hash_reset(PassArgs a) {
 __global__ __launch_bounds__(kBlock) void k_hash_refill(PassArgs a) {
   if (!*a.hflag) return;
   const int64_t total = a.n * a.k;
+  int32_t claimed = 0;
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < total;
        j += (int64_t)gridDim.x * kBlock) {
     const int64_t v = j / a.k;
     const int i = (int)(j - v * a.k);
-    atomicAdd(counter(a.t, hslot(a.t, hkey(a.t, i, a.C[v], a.Lvm[j]))), 1);
+    atomicAdd(counter(a.t, hslot(a.t, hkey(a.t, i, a.C[v], a.Lvm[j]), claimed)), 1);
+  }
+  flush_claims(a.t, claimed);
+}
+
+// Member lists of the clusters at the start of the pass (mstart holds the
+// exclusive scan of the sizes, mcnt is zeroed): a counting sort of C.
+__global__ __launch_bounds__(kBlock) void k_member_fill(PassArgs a) {
+  if (a.ctl->done) return;
+  for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < a.n;
+       v += (int64_t)gridDim.x * kBlock) {
+    const int32_t x = a.C[v];
+    if (a.s[x] <= kMemberSumMax)  // larger clusters are probed, not listed
+      a.members[a.mstart[x] + atomicAdd(&a.mcnt[x], 1)] = (int32_t)v;
   }
 }
 
@@ -826,6 +906,11 @@ void launch_ctl_init(Ctl* ctl, const int64_t* acc, int32_t k, int32_t max_rounds
 
 void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, hipStream_t st,
                   hipEvent_t score_begin, hipEvent_t score_end) {
+  if (a.members) {
+    launch_scan(a.s, a.mstart, a.K0, a.mscan_tmp, st);
+    launch_fill_i32(a.mcnt, a.K0, 0, st);
+    k_member_fill<<<grid_apply, kBlock, 0, st>>>(a);
+  }
   if (score_begin) (void)hipEventRecord(score_begin, st);
   switch (lanes) {
     case 0:

@@ -249,12 +249,14 @@ __global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
   // partition-major input labels (coalesced when stride is 1) mapped to their ids
   const int32_t* p = labels[i];
   const int32_t* map = fmap + loff[i];
+  int32_t claimed = 0;
   for (int64_t j = j0 + threadIdx.x; j < j1; j += kBlock) {
     const int64_t v = j * stride;
     const int32_t x = C[v], l = map[p[v]];
     if (lds) atomicAdd(&h[x * Li + l], 1);
-    else atomicAdd(counter(t, cell_upd(t, i, x, l)), 1);
+    else atomicAdd(counter(t, cell_upd(t, i, x, l, claimed)), 1);
   }
+  if (t.hashed) flush_claims(t, claimed);
   if (lds) {
     __syncthreads();
     for (int j = threadIdx.x; j < entries; j += kBlock)
@@ -323,11 +325,27 @@ __global__ __launch_bounds__(kBlock) void k_label_hist(const int32_t* const* __r
                                                        const int32_t* __restrict__ fmap,
                                                        const int64_t* __restrict__ toff, int64_t n,
                                                        int32_t* __restrict__ hist) {
+  __shared__ int32_t h[kLdsHist];
   const int i = blockIdx.y;
   const int32_t* p = labels[i];
   const int32_t* map = fmap + loff[i];
   int32_t* hi = hist + toff[i];
-  for (int64_t v = gtid(); v < n; v += gstride()) atomicAdd(&hi[map[p[v]]], 1);
+  const int64_t Li = toff[i + 1] - toff[i];
+  const bool lds = Li <= kLdsHist;  // few labels: count in LDS, flush once
+  if (lds) {
+    for (int64_t l = threadIdx.x; l < Li; l += kBlock) h[l] = 0;
+    __syncthreads();
+  }
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    const int32_t l = map[p[v]];
+    if (lds) atomicAdd(&h[l], 1);
+    else atomicAdd(&hi[l], 1);
+  }
+  if (lds) {
+    __syncthreads();
+    for (int64_t l = threadIdx.x; l < Li; l += kBlock)
+      if (h[l]) atomicAdd(&hi[l], h[l]);
+  }
 }
 
 // sum of squared slot counts
