@@ -14,8 +14,10 @@
  * Conventions for every entry point:
  *  - Array arguments are DEVICE pointers (memory on the current HIP device,
  *    e.g. a torch tensor's data_ptr), unless a comment says "host".  The
- *    caller owns every buffer; the library keeps no pointer after a call
- *    returns and allocates its own workspace on the given stream.
+ *    caller owns every buffer; the library keeps no pointer to them after a
+ *    call returns.  Its own workspace is kept between calls, per device and
+ *    stream (at most 64 GiB in total; mcc_release_workspace frees it), so
+ *    that repeated calls allocate nothing.
  *  - `stream` is a hipStream_t passed as void*; NULL means the default
  *    stream.  Each call is stream-ordered and returns only once its results
  *    are complete (it synchronises with the stream).
@@ -58,6 +60,14 @@ extern "C" {
                                  pass (costs nnz * 8 bytes and a list build;
                                  pays off with many passes; a tuning knob,
                                  results do not depend on it) */
+#define MCC_F_SYMMETRIC 0x40u /* the caller states that the graph is symmetric
+                                 (every arc (v, u) has a reverse arc (u, v)):
+                                 candidate sets are then carried over between
+                                 passes for vertices with no moved neighbour.
+                                 Results do not change; on a graph that is not
+                                 symmetric they may differ from the exact
+                                 method, so with MCC_F_VALIDATE the library
+                                 checks the property (MCC_EGRAPH if it fails) */
 #define MCC_F_HASH_TABLES 0x20u /* keep the contingency counts in one
                                    open-addressing hash table even where dense
                                    tables fit (they are chosen automatically
@@ -345,6 +355,11 @@ int mcc_group_from_distances(const int64_t* dist, int32_t k, int64_t lambda, int
 int mcc_group_partitions(const int32_t* const* labels, int32_t k, int64_t n, int64_t lambda,
                          int32_t* group, int32_t* ngroups, int64_t* lambda_used, int64_t* dist,
                          void* stream);
+
+/* Free the workspace the library keeps between calls (every device and
+ * stream).  Call it with no other libmcc call in flight.  Returns 0 or
+ * MCC_EDEVICE. */
+int mcc_release_workspace(void);
 
 /* Static text for a return code (for MCC_EDEVICE, the last HIP error seen
  * on this thread). */

@@ -15,13 +15,13 @@ LIB_PATH = os.path.join(PKG, "libmcc.so")
 
 MCC_OK, MCC_EINVAL, MCC_EGRAPH, MCC_ENOMEM, MCC_EDEVICE, MCC_ENOTSUP = 0, -1, -2, -3, -4, -5
 MCC_F_VALIDATE, MCC_F_TRACE, MCC_F_LITERAL, MCC_F_PROFILE = 0x1, 0x2, 0x4, 0x8
-MCC_F_ARC_CACHE, MCC_F_HASH_TABLES = 0x10, 0x20
+MCC_F_ARC_CACHE, MCC_F_HASH_TABLES, MCC_F_SYMMETRIC = 0x10, 0x20, 0x40
 
 # every function include/mcc.h declares
 EXPORTS = ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize",
            "mcc_consensus_batch", "mcc_batch_tune", "mcc_tune_save", "mcc_tune_load",
            "mcc_compare", "mcc_split_join_matrix", "mcc_group_from_distances",
-           "mcc_group_partitions", "mcc_strerror")
+           "mcc_group_partitions", "mcc_release_workspace", "mcc_strerror")
 MCC_TUNE_LANES, MCC_TUNE_MAX_BUCKETS = 5, 160
 TUNE_LANES = (4, 8, 16, 32, 64)
 
@@ -130,8 +130,9 @@ def lib():
         L.mcc_split_join_matrix.argtypes = [p, i32, i64, p, p]
         L.mcc_group_from_distances.argtypes = [p, i32, i64, p, p, p]
         L.mcc_group_partitions.argtypes = [p, i32, i64, i64, p, p, p, p, p]
+        L.mcc_release_workspace.argtypes = []
         for f in ("mcc_compare", "mcc_split_join_matrix", "mcc_group_from_distances",
-                  "mcc_group_partitions"):
+                  "mcc_group_partitions", "mcc_release_workspace"):
             getattr(L, f).restype = ctypes.c_int
         L.mcc_strerror.argtypes = [ctypes.c_int]
         L.mcc_strerror.restype = ctypes.c_char_p
@@ -401,3 +402,8 @@ def consensus_groups(row_ptr, col, labels, lam=-1, init="first", max_rounds=0, f
         if c != 0:
             raise MccError(c, lib().mcc_strerror(c).decode())
     return g, used, outs, stats
+
+
+def release_workspace():
+    """Free the device workspace the library keeps between calls."""
+    _check(lib().mcc_release_workspace())

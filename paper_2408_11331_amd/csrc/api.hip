@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -51,13 +53,58 @@ struct Status {
 
 // Stream-ordered scratch allocations, released on the same stream when the
 // call returns (the pool keeps them warm for the next call).
+// Workspace chunks kept between calls, per (device, stream): a call takes the
+// chunks its stream left and gives them back when it returns, so steady-state
+// calls allocate and free nothing (allocation and free calls cost about a
+// tenth of a millisecond each).  Reuse on the same stream is ordered by the
+// stream.  Chunks beyond kCachedMax bytes in total are freed on return;
+// mcc_release_workspace frees the rest.
+struct Chunk {
+  void* p;
+  size_t size;
+};
+
+struct ChunkCache {
+  std::mutex m;
+  std::map<std::pair<int, hipStream_t>, std::vector<Chunk>> free;
+  size_t bytes = 0;
+};
+
+ChunkCache& chunk_cache() {
+  static ChunkCache* c = new ChunkCache;  // never destroyed: may outlive static teardown
+  return *c;
+}
+
+constexpr size_t kCachedMax = (size_t)64 << 30;
+
 class Arena {
  public:
-  explicit Arena(hipStream_t st) : st_(st) {}
+  explicit Arena(hipStream_t st) : st_(st) {
+    (void)hipGetDevice(&dev_);
+    ChunkCache& c = chunk_cache();
+    std::lock_guard<std::mutex> lock(c.m);
+    auto it = c.free.find({dev_, st_});
+    if (it != c.free.end()) {
+      avail_.swap(it->second);
+      for (const Chunk& k : avail_) c.bytes -= k.size;
+      c.free.erase(it);
+    }
+  }
   ~Arena() {
-    // host staging buffers may still feed queued copies: drain first
+    // kernels and queued copies may still use the chunks: drain first
     (void)hipStreamSynchronize(st_);
-    for (void* p : ptrs_) (void)hipFreeAsync(p, st_);
+    ChunkCache& c = chunk_cache();
+    std::lock_guard<std::mutex> lock(c.m);
+    std::vector<Chunk>& keep = c.free[{dev_, st_}];
+    for (std::vector<Chunk>* list : {&used_, &avail_})
+      for (const Chunk& k : *list) {
+        if (c.bytes + k.size <= kCachedMax) {
+          keep.push_back(k);
+          c.bytes += k.size;
+        } else {
+          (void)hipFree(k.p);
+        }
+      }
   }
   // Host buffer that lives as long as the arena (source of async copies).
   template <class T>
@@ -66,23 +113,57 @@ class Arena {
     memcpy(staging_.back().data(), src.data(), src.size() * sizeof(T));
     return reinterpret_cast<T*>(staging_.back().data());
   }
+  // Device buffer of `count` elements, 256-byte aligned.  Requests are
+  // carved from chunks of kChunk bytes (a larger request gets a chunk of its
+  // own), taken from the stream's cached chunks when one is large enough.
   template <class T>
   T* get(int64_t count) {
     if (count < 1) count = 1;
-    void* p = nullptr;
-    hipError_t e = hipMallocAsync(&p, (size_t)count * sizeof(T), st_);
-    if (e == hipErrorOutOfMemory) {
-      (void)hipGetLastError();
-      throw NoMem{};
+    const size_t bytes = ((size_t)count * sizeof(T) + 255) & ~(size_t)255;
+    if (bytes <= left_) {
+      void* r = next_;
+      next_ += bytes;
+      left_ -= bytes;
+      return static_cast<T*>(r);
     }
-    hipck(e, "hipMallocAsync");
-    ptrs_.push_back(p);
-    return static_cast<T*>(p);
+    const Chunk k = chunk(std::max(bytes, kChunk));
+    if (bytes >= kChunk) return static_cast<T*>(k.p);  // own chunk; keep the current one
+    next_ = static_cast<unsigned char*>(k.p) + bytes;
+    left_ = k.size - bytes;
+    return static_cast<T*>(k.p);
   }
 
  private:
+  // The smallest cached chunk of at least `size` bytes, else a new one.
+  Chunk chunk(size_t size) {
+    size_t best = avail_.size();
+    for (size_t j = 0; j < avail_.size(); ++j)
+      if (avail_[j].size >= size && (best == avail_.size() || avail_[j].size < avail_[best].size))
+        best = j;
+    Chunk k;
+    if (best < avail_.size()) {
+      k = avail_[best];
+      avail_.erase(avail_.begin() + best);
+    } else {
+      void* p = nullptr;
+      hipError_t e = hipMalloc(&p, size);
+      if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        throw NoMem{};
+      }
+      hipck(e, "hipMalloc");
+      k = {p, size};
+    }
+    used_.push_back(k);
+    return k;
+  }
+
+  static constexpr size_t kChunk = (size_t)16 << 20;
   hipStream_t st_;
-  std::vector<void*> ptrs_;
+  int dev_ = 0;
+  std::vector<Chunk> used_, avail_;
+  unsigned char* next_ = nullptr;
+  size_t left_ = 0;
   std::vector<std::vector<unsigned char>> staging_;
 };
 
@@ -526,6 +607,15 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
     a.cells = S.total;
     a.nnz = nnz;
     a.arcs_aligned = ((uintptr_t)g->col & 15) == 0 ? 1 : 0;  // ac comes from the arena (aligned)
+    if ((flags & MCC_F_SYMMETRIC) && (flags & MCC_F_VALIDATE)) {
+      int32_t* serr = ar.get<int32_t>(1);
+      launch_fill_i32(serr, 1, 0, st);
+      launch_check_symmetric(g->row_ptr, g->col, n, serr, st);
+      int32_t hs = 0;
+      d2h(&hs, serr, 1, st);
+      sync(st);
+      if (hs) throw Status{MCC_EGRAPH};
+    }
     a.hflag = S.t.hashed ? ar.get<int32_t>(1) : nullptr;
     a.K0 = S.K0;
     if (S.t.hashed) {
@@ -545,6 +635,13 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
 
     // the tiled scorer packs cluster ids in 24 bits
     const int lanes = (lanes_req == 0 && S.K0 >= (1 << 24)) ? 64 : lanes_req;
+    if ((flags & MCC_F_SYMMETRIC) && lanes == 0) {  // candidate sets carried over
+      a.dirty = ar.get<int32_t>(n);
+      a.cnum = ar.get<int32_t>(n);
+      a.ccache = ar.get<int32_t>(n * kCacheCand);
+      launch_fill_i32(a.dirty, n, 1, st);
+      launch_fill_i32(a.cnum, n, -1, st);
+    }
     const int sms = device_sms();
     const int64_t blocks_needed =
         lanes ? (n * lanes + kBlock - 1) / kBlock : (n + kBlock - 1) / kBlock;
@@ -1428,6 +1525,23 @@ int mcc_group_partitions(const int32_t* const* labels, int32_t k, int64_t n, int
   const int rc = mcc_split_join_matrix(labels, k, n, d, stream);
   if (rc != MCC_OK) return rc;
   return mcc_group_from_distances(d, k, lambda, group, ngroups, lambda_used);
+}
+
+int mcc_release_workspace(void) {
+  ChunkCache& c = chunk_cache();
+  std::lock_guard<std::mutex> lock(c.m);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  int rc = MCC_OK;
+  for (auto& kv : c.free) {
+    if (hipSetDevice(kv.first.first) != hipSuccess) rc = MCC_EDEVICE;
+    for (const Chunk& k : kv.second)
+      if (hipFree(k.p) != hipSuccess) rc = MCC_EDEVICE;
+  }
+  c.free.clear();
+  c.bytes = 0;
+  (void)hipSetDevice(cur);
+  return rc;
 }
 
 int mcc_tune_save(const mcc_tune_table* t, const char* path) {

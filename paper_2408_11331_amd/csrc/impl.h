@@ -184,7 +184,8 @@ void launch_cluster_assign(const int32_t* init, int64_t n, const int32_t* cmap, 
 void launch_iota(int32_t* a, int64_t n, hipStream_t st);
 void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st);
 void launch_fill_u64(uint64_t* a, int64_t n, uint64_t v, hipStream_t st);
-// Counts every stride-th vertex (stride 1: the exact tables).
+// Counts a sample of the vertices, runs of 64 consecutive vertices one run
+// in every `stride` (stride 1: all vertices, the exact tables).
 void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t* loff,
                   const int32_t* fmap, int64_t n, int32_t k, int32_t K0, Tables t,
                   hipStream_t st, int64_t stride = 1);
@@ -211,6 +212,9 @@ void launch_copy_i32(const int32_t* src, int32_t* dst, int64_t n, hipStream_t st
 void launch_narrow(const int32_t* src, void* dst, int32_t bytes, int64_t n, hipStream_t st);
 void launch_validate_csr(const int64_t* row_ptr, const int32_t* col, int64_t n, int64_t nnz,
                          int32_t* err, hipStream_t st);
+// err |= kErrGraph unless every arc (v, u) has a reverse arc (u, v).
+void launch_check_symmetric(const int64_t* row_ptr, const int32_t* col, int64_t n,
+                            int32_t* err, hipStream_t st);
 void launch_finish(const int32_t* C, const int32_t* rawid, int64_t n, int32_t* out,
                    hipStream_t st);
 void launch_count_nonzero(const int32_t* a, int64_t n, int32_t* count, hipStream_t st);
@@ -280,7 +284,17 @@ struct PassArgs {
   int32_t cn_bytes;
   int32_t arcs_aligned;  // col (and ac) start on a 16-byte boundary
   int64_t nnz;
+  // Symmetric graphs (every arc has its reverse): candidate sets carried
+  // over between passes.  A vertex is dirty when it or a neighbour moved in
+  // the previous pass (a move marks the mover and its out-neighbours, which
+  // are its in-neighbours); a clean vertex with a cached set (cnum >= 0)
+  // skips its arcs.  Null when off.
+  int32_t* dirty;     // n
+  int32_t* cnum;      // n: cached candidate count, -1 none
+  int32_t* ccache;    // n * kCacheCand
 };
+
+constexpr int kCacheCand = 8;  // candidate clusters cached per vertex
 
 // Compile-time variants: CN is the narrow copy's width in bytes (0: read the
 // per-arc cache), IL selects the interleaved table layout.

@@ -291,6 +291,8 @@ void k_score_tile(PassArgs a) {
   __shared__ int32_t s_nc[kBlock];    // candidates of each vertex
   __shared__ int32_t s_def[kBlock];   // 1: vertex deferred to the group scorer
   __shared__ int32_t s_cur[kBlock];   // fill cursor of the vertex's run
+  __shared__ int32_t s_clean[kBlock]; // 1: candidate set taken from the cache
+  __shared__ int32_t s_np;            // pairs that fit the pair arrays
   __shared__ int32_t s_set[kSetSlots];
   __shared__ int32_t s_cl[kPairMax];   // pair keys (vertex << 24 | cluster), run per vertex
   __shared__ int32_t s_S[kPairMax];    // agreement sum of each pair
@@ -307,7 +309,13 @@ void k_score_tile(PassArgs a) {
     const int64_t a0 = a.row_ptr[v0];
     for (int j = t; j <= nv; j += kBlock) s_off[j] = (int32_t)(a.row_ptr[v0 + j] - a0);
     s_c[t] = t < nv ? a.C[v0 + t] : -1;
-    s_nc[t] = 0;
+    int32_t cached = -1;  // candidates of a clean vertex, from the previous pass
+    if (a.dirty && t < nv) {
+      if (!a.dirty[v0 + t]) cached = a.cnum[v0 + t];
+      a.dirty[v0 + t] = 0;  // this pass's moves mark it again
+    }
+    s_clean[t] = cached >= 0;
+    s_nc[t] = cached > 0 ? cached : 0;
     s_def[t] = 0;
     for (int j = t; j < kSetSlots; j += kBlock) s_set[j] = -1;
     __syncthreads();
@@ -340,13 +348,6 @@ void k_score_tile(PassArgs a) {
           }
         }
       }
-      int32_t cu[U];
-#pragma unroll
-      for (int r = 0; r < U; ++r) {
-        const int32_t j = jt + r;
-        cu[r] = -1;
-        if (j >= 0 && j < A) cu[r] = CN ? cn_load_t<CN>(a, 0, hd[r]) : hd[r];
-      }
       int lo = 0;
       const int32_t j0 = max(jt, 0);
       if (j0 < A) {
@@ -357,12 +358,24 @@ void k_score_tile(PassArgs a) {
           else hi = mid - 1;
         }
       }
-      int32_t prev = -1;  // the last key this thread placed: repeats skip the set
+      // tails of the thread's arcs; clean tails skip the gather
+      int tl[U];
 #pragma unroll
       for (int r = 0; r < U; ++r) {
         const int32_t j = jt + r;
+        tl[r] = -1;
         if (j < 0 || j >= A) continue;
         while (s_off[lo + 1] <= j) ++lo;
+        if (!s_clean[lo]) tl[r] = lo;
+      }
+      int32_t cu[U];
+#pragma unroll
+      for (int r = 0; r < U; ++r) cu[r] = tl[r] >= 0 ? (CN ? cn_load_t<CN>(a, 0, hd[r]) : hd[r]) : -1;
+      int32_t prev = -1;  // the last key this thread placed: repeats skip the set
+#pragma unroll
+      for (int r = 0; r < U; ++r) {
+        if (tl[r] < 0) continue;
+        lo = tl[r];
         const int32_t x = cu[r];
         if (x == s_c[lo]) continue;
         const int32_t key = (lo << 24) | x;
@@ -388,11 +401,23 @@ void k_score_tile(PassArgs a) {
       }
     }
     __syncthreads();
-    // runs of candidates per vertex and the list of boundary vertices, from
-    // one scan of (candidates << 16 | is boundary)
     const int nc = s_nc[t];
-    const bool def = t < nv && s_def[t];
-    const bool is_b = t < nv && nc > 0 && !def;
+    bool def = t < nv && s_def[t];
+    bool is_b = t < nv && nc > 0 && !def;
+    // one run per boundary vertex: its own cluster, then its candidates.
+    // Candidates taken from the key set number at most kSetSlots, but cached
+    // sets bypass it: a run that would pass the end of the pair arrays
+    // defers its vertex (and the runs after it) to the group scorer.
+    int32_t npairs;
+    const int32_t coff = block_exclusive_scan(is_b ? nc + 1 : 0, &npairs);
+    if (t == 0) s_np = npairs;
+    __syncthreads();
+    if (is_b && coff + nc + 1 > kPairMax) {
+      is_b = false;
+      def = true;
+      s_def[t] = 1;
+      atomicMin(&s_np, coff);
+    }
     if (t < nv) {
       const int64_t v = v0 + t;
       if (def) {
@@ -405,12 +430,15 @@ void k_score_tile(PassArgs a) {
         boundary += 1;
       }
     }
-    // one run per boundary vertex: its own cluster, then its candidates
-    int32_t npairs;
-    const int32_t coff = block_exclusive_scan(is_b ? nc + 1 : 0, &npairs);
     s_cur[t] = coff + 1;
-    if (is_b) s_cl[coff] = (t << 24) | s_c[t];
+    if (is_b) {
+      s_cl[coff] = (t << 24) | s_c[t];
+      if (s_clean[t])
+        for (int j = 0; j < nc; ++j)
+          s_cl[coff + 1 + j] = (t << 24) | a.ccache[(v0 + t) * kCacheCand + j];
+    }
     __syncthreads();
+    npairs = s_np;
     for (int h = t; h < kSetSlots; h += kBlock) {
       const int32_t key = s_set[h];
       if (key == -1) continue;
@@ -419,6 +447,16 @@ void k_score_tile(PassArgs a) {
       s_cl[atomicAdd(&s_cur[tv], 1)] = key;
     }
     __syncthreads();
+    // cache the sets found this pass (interior vertices cache "none")
+    if (a.dirty && t < nv && !s_clean[t]) {
+      const int64_t v = v0 + t;
+      if (def || nc > kCacheCand) {
+        a.cnum[v] = -1;
+      } else {
+        for (int j = 0; j < nc; ++j) a.ccache[v * kCacheCand + j] = s_cl[coff + 1 + j] & 0xffffff;
+        a.cnum[v] = nc;
+      }
+    }
     constexpr int kStride = (kBlock / kProbeLanes) * kProbeBatch;
     auto pair_at = [&](int p, int32_t& x, uint32_t& row) {
       x = -1;
@@ -696,6 +734,15 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
   }
 }
 
+// Vertex w moved: it and its out-neighbours (its in-neighbours, the graph
+// being symmetric) recompute their candidate sets next pass.
+__device__ inline void mark_dirty(const PassArgs& a, int64_t w, int lane) {
+  if (!a.dirty) return;
+  if (lane == 0) a.dirty[w] = 1;
+  const int64_t b = a.row_ptr[w], e = a.row_ptr[w + 1];
+  for (int64_t p = b + lane; p < e; p += 64) a.dirty[a.col[p]] = 1;
+}
+
 // Vertex w now sits in cluster c: every arc pointing at w learns it.
 __device__ inline void relabel_in_arcs(const PassArgs& a, int64_t w, int32_t c, int lane) {
   if (!a.ac) return;
@@ -741,6 +788,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(PassArgs a) {
             cn_store(a, w, pw);
           }
           relabel_in_arcs(a, w, pw, lane);
+          mark_dirty(a, w, lane);
         } else {
           move_counts(a, w, from, pw, -1, lane, &ds2);  // undo the batch
           if (lane == 0) {
@@ -768,7 +816,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(PassArgs a) {
             cn_store(a, w, pw);
           }
         }
-        if (pw >= 0) relabel_in_arcs(a, w, pw, lane);
+        if (pw >= 0) {
+          relabel_in_arcs(a, w, pw, lane);
+          mark_dirty(a, w, lane);
+        }
       }
     }
   }

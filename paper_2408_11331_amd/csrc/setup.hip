@@ -222,6 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_u64(uint64_t* __restrict__ a, i
 
 // ---- contingency tables ------------------------------------------------------
 constexpr int kLdsHist = 16384;  // int32 entries privatised in LDS (64 KiB)
+constexpr int64_t kSampleRun = 64;  // vertices per run of a sampled build
 
 // Workgroup (b, i) counts the pairs (C(v), P_i(v)) of its vertex range for
 // partition i.  When partition i's K0 x L[i] slice fits kLdsHist entries the
@@ -237,12 +238,20 @@ __global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
   const int32_t Li = t.L[i];
   const int64_t entries = (int64_t)K0 * Li;
   const bool lds = !t.hashed && entries <= kLdsHist;
+  // Counts concentrate on few cells (a cluster's members mostly share their
+  // labels), so threads spread over up to 8 copies of a small slice: fewer
+  // atomics on one LDS word at a time.
+  const int copies = lds ? (int)min((int64_t)8, kLdsHist / max(entries, (int64_t)1)) : 1;
+  int32_t* hc = h + (threadIdx.x % copies) * entries;
   if (lds) {
-    for (int j = threadIdx.x; j < entries; j += kBlock) h[j] = 0;
+    for (int j = threadIdx.x; j < entries * copies; j += kBlock) h[j] = 0;
     __syncthreads();
   }
-  // every stride-th vertex (stride 1: all of them)
-  const int64_t ns = (n + stride - 1) / stride;
+  // a sample of the vertices: runs of kSampleRun consecutive vertices, one
+  // run every stride runs, so that the sample is read with whole cache
+  // lines (stride 1: all vertices)
+  const int64_t runs = (n + kSampleRun - 1) / kSampleRun;
+  const int64_t ns = ((runs + stride - 1) / stride) * kSampleRun;
   const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
   const int64_t j0 = (int64_t)blockIdx.x * per;
   const int64_t j1 = min(ns, j0 + per);
@@ -251,19 +260,23 @@ __global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
   const int32_t* map = fmap + loff[i];
   int32_t claimed = 0;
   for (int64_t j = j0 + threadIdx.x; j < j1; j += kBlock) {
-    const int64_t v = j * stride;
+    const int64_t v = (j / kSampleRun) * (kSampleRun * stride) + j % kSampleRun;
+    if (v >= n) continue;
     const int32_t x = C[v], l = map[p[v]];
-    if (lds) atomicAdd(&h[x * Li + l], 1);
+    if (lds) atomicAdd(&hc[x * Li + l], 1);
     else atomicAdd(counter(t, cell_upd(t, i, x, l, claimed)), 1);
   }
   if (t.hashed) flush_claims(t, claimed);
   if (lds) {
     __syncthreads();
-    for (int j = threadIdx.x; j < entries; j += kBlock)
-      if (h[j]) {
+    for (int j = threadIdx.x; j < entries; j += kBlock) {
+      int32_t c = 0;
+      for (int q = 0; q < copies; ++q) c += h[q * entries + j];
+      if (c) {
         const int32_t x = j / Li;
-        atomicAdd(&t.N[cell(t, i, x, j - x * Li)], h[j]);
+        atomicAdd(&t.N[cell(t, i, x, j - x * Li)], c);
       }
+    }
   }
 }
 
@@ -361,6 +374,24 @@ __global__ __launch_bounds__(kBlock) void k_slot_sumsq(Tables t, int64_t* __rest
 }
 
 // ---- validation, output ----------------------------------------------------
+// Every arc (v, u) must have a reverse arc (u, v): a search of u's row (work
+// sum over u of deg(u)^2; a check, not on the solve path).
+__global__ __launch_bounds__(kBlock) void k_check_symmetric(const int64_t* __restrict__ row_ptr,
+                                                            const int32_t* __restrict__ col,
+                                                            int64_t n, int32_t* __restrict__ err) {
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    bool ok = true;
+    for (int64_t j = row_ptr[v]; j < row_ptr[v + 1] && ok; ++j) {
+      const int32_t u = col[j];
+      if (u == v) continue;
+      bool found = false;
+      for (int64_t p = row_ptr[u]; p < row_ptr[u + 1] && !found; ++p) found = col[p] == v;
+      ok = found;
+    }
+    if (!ok) atomicOr(err, kErrGraph);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_validate_csr(const int64_t* __restrict__ row_ptr,
                                                          const int32_t* __restrict__ col,
                                                          int64_t n, int64_t nnz,
@@ -602,7 +633,7 @@ void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t
                   hipStream_t st, int64_t stride) {
   // enough workgroups per partition to fill the chip, few enough that the
   // LDS flush stays small next to the counting
-  int64_t per_part = ((n + stride - 1) / stride + 4095) / 4096;
+  int64_t per_part = ((n + stride - 1) / stride + 4095) / 4096;  // about the sample size
   if (per_part > 64) per_part = 64;
   if (per_part < 1) per_part = 1;
   dim3 g((unsigned)per_part, k);
@@ -637,6 +668,11 @@ void launch_objective0_hashed(const Tables& t, const int32_t* const* dlabels, co
   k_label_hist<<<g, kBlock, 0, st>>>(dlabels, loff, fmap, t.toff, n, hist);
   k_sumsq<<<grid_for(total_labels, kBlock, 2048), kBlock, 0, st>>>(hist, total_labels, acc + 1);
   k_slot_sumsq<<<grid_for((int64_t)t.hmask + 1, kBlock * 4, 4096), kBlock, 0, st>>>(t, acc + 2);
+}
+
+void launch_check_symmetric(const int64_t* row_ptr, const int32_t* col, int64_t n,
+                            int32_t* err, hipStream_t st) {
+  if (n > 0) k_check_symmetric<<<grid_for(n, kBlock, 4096), kBlock, 0, st>>>(row_ptr, col, n, err);
 }
 
 void launch_in_degree(const int32_t* col, int64_t nnz, int32_t* indeg, hipStream_t st) {

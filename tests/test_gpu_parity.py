@@ -111,6 +111,8 @@ def test_random_instances(mcc, seed, n, k, init):
         assert_same(run_gpu(mcc, inst, ini, lanes=lanes), o)
     # neighbour clusters from the per-arc cache instead of gathers
     assert_same(run_gpu(mcc, inst, ini, flags=mcc.MCC_F_ARC_CACHE), o)
+    # candidate sets carried over between passes (the graphs are symmetric)
+    assert_same(run_gpu(mcc, inst, ini, flags=mcc.MCC_F_SYMMETRIC | mcc.MCC_F_VALIDATE), o)
     # counts in the open-addressing table instead of dense tables
     for lanes in (0, [64, 32, 16, 8, 4][seed % 5]):
         g = run_gpu(mcc, inst, ini, lanes=lanes, flags=mcc.MCC_F_HASH_TABLES)
@@ -148,6 +150,35 @@ def test_arc_cache_workloads(mcc):
     announce("arc cache sbm_small/gmm_knn")
     for inst in (synth.sbm_small(), synth.gmm_knn(n=5000)):
         assert_same(run_gpu(mcc, inst, flags=mcc.MCC_F_ARC_CACHE), run_oracle(inst))
+
+
+def test_symmetric_candidate_cache_workloads(mcc):
+    # carried-over candidate sets on the workloads, both starts, and with the
+    # arc cache; the singleton start leaves many vertices with more than the
+    # cached number of candidates
+    announce("symmetric sbm_small/gmm_knn/lfr")
+    sym = mcc.MCC_F_SYMMETRIC
+    for inst in (synth.sbm_small(), synth.gmm_knn(n=20000), synth.lfr(n=30000, k=12)):
+        o = run_oracle(inst)
+        assert_same(run_gpu(mcc, inst, flags=sym), o)
+        assert_same(run_gpu(mcc, inst, flags=sym | mcc.MCC_F_ARC_CACHE), o)
+        assert_same(run_gpu(mcc, inst, None, flags=sym), run_oracle(inst, None))
+
+
+def test_symmetric_flag_validation(mcc):
+    announce("symmetric validation")
+    inst = synth.random_instance(300, 4, 6.0, 5, seed=12)
+    rp, col = inst.row_ptr.copy(), inst.col.copy()
+    # drop one direction of an edge: no longer symmetric
+    j = int(np.argmax(np.diff(rp) > 0))
+    u = int(col[rp[j]])
+    col[rp[j]] = j if u != j else (j + 1) % 300
+    bad = synth.Instance("asym", rp, col, inst.labels, inst.init, inst.init, {})
+    with pytest.raises(mcc.MccError) as e:
+        run_gpu(mcc, bad, flags=mcc.MCC_F_SYMMETRIC | mcc.MCC_F_VALIDATE)
+    assert e.value.code == mcc.MCC_EGRAPH
+    # without the flag the same graph solves exactly
+    assert_same(run_gpu(mcc, bad, flags=mcc.MCC_F_VALIDATE), run_oracle(bad))
 
 
 def test_literal_self_term_ablation(mcc):
