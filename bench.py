@@ -257,6 +257,9 @@ def main():
     ap.add_argument("--budget-gib", type=int, default=64, help="served: HBM admission budget")
     ap.add_argument("--n", type=int, default=0, help="override the vertex count")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--no-symmetric", dest="symmetric", action="store_false",
+                    help="do not pass MCC_F_SYMMETRIC (the generated graphs are symmetric, "
+                         "so by default the library may carry candidate sets over passes)")
     ap.add_argument("--init", default="p0", choices=["p0", "singleton"],
                     help="consensus start: input partition 0, or singletons (the paper's)")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
@@ -298,9 +301,11 @@ def main():
     out = torch.empty(inst.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
+    base_flags = mcc.MCC_F_SYMMETRIC if args.symmetric else 0
+
     def solve(flags=0, trace=False):
-        return mcc.consensus(rp, col, lab, ini, flags=flags, lanes=args.lanes, out=out,
-                             stream=stream, trace=trace)
+        return mcc.consensus(rp, col, lab, ini, flags=flags | base_flags, lanes=args.lanes,
+                             out=out, stream=stream, trace=trace)
 
     for j in range(args.warmup):
         solve()
@@ -348,6 +353,7 @@ def main():
             "workload": args.workload, "n": inst.n, "nnz": inst.nnz, "k": inst.k,
             "init": "input partition 0" if args.init == "p0" else "singletons",
             "tables": ["dense blocked", "dense interleaved", "hashed"][st_ref["tables"]],
+            "symmetric_flag": bool(args.symmetric),
             "passes": passes, "moves": st_ref["moves"],
             "candidate_evals_per_solve": st_ref["candidate_evals"],
             "boundary_vertex_passes": st_ref["boundary"], "objective": st_ref["objective"],
