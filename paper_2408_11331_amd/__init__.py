@@ -161,12 +161,30 @@ def _dev_i32(t, name):
 
 
 def _label_ptrs(labels):
-    """Labels as a (k, n) tensor or a sequence of n-vectors -> ctypes array."""
-    rows = [labels[i] for i in range(labels.shape[0])] if hasattr(labels, "shape") and \
-        labels.dim() == 2 else list(labels)
-    rows = [_dev_i32(r, "labels") for r in rows]
+    """Labels as a (k, n) tensor or a sequence of n-vectors -> (objects to
+    keep alive, ctypes array of row pointers)."""
+    if hasattr(labels, "shape") and labels.dim() == 2:
+        t = _dev_i32(labels, "labels")  # contiguous: row i starts i * n elements in
+        k, n = t.shape
+        base, step = t.data_ptr(), n * 4
+        arr = (ctypes.c_void_p * max(1, k))(*[base + i * step for i in range(k)])
+        return _Rows(t, k, n), arr
+    rows = [_dev_i32(r, "labels") for r in labels]
     arr = (ctypes.c_void_p * max(1, len(rows)))(*[r.data_ptr() for r in rows])
     return rows, arr
+
+
+class _Rows:
+    """The rows of a (k, n) tensor without slicing it: len() and numel()."""
+
+    def __init__(self, t, k, n):
+        self.t, self.k, self.n = t, k, n
+
+    def __len__(self):
+        return self.k
+
+    def __getitem__(self, i):
+        return self.t[i]
 
 
 def consensus(row_ptr, col, labels, init=None, *, max_rounds=0, flags=0, lanes=0,

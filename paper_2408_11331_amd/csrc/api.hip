@@ -194,6 +194,31 @@ bool device_visible(const void* p) {
          at.devicePointer != nullptr;
 }
 
+// device_visible over many pointers: the allocation range of every pointer
+// found visible is remembered, and a pointer inside a remembered range needs
+// no query (a batch passes tens of pointers per instance, mostly into a few
+// large allocations, and each query costs microseconds).
+class VisibleRanges {
+ public:
+  bool check(const void* p) {
+    if (!p) return false;
+    const uintptr_t q = (uintptr_t)p;
+    for (const auto& r : ranges_)
+      if (q >= r.first && q < r.second) return true;
+    if (!device_visible(p)) return false;
+    void* base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess && size > 0)
+      ranges_.emplace_back((uintptr_t)base, (uintptr_t)base + size);
+    else
+      (void)hipGetLastError();
+    return true;
+  }
+
+ private:
+  std::vector<std::pair<uintptr_t, uintptr_t>> ranges_;
+};
+
 // Wait for the stream and surface any launch or execution error.
 void sync(hipStream_t st) {
   HIPCK(hipStreamSynchronize(st));
@@ -887,14 +912,15 @@ int64_t pow2_ceil(int64_t x) {
   return p;
 }
 
-bool problem_ok(const mcc_problem& p, bool need_out) {
+bool problem_ok(const mcc_problem& p, bool need_out, VisibleRanges& vis) {
   const int64_t n = p.g.n;
   bool ok = p.k >= 1 && n >= 0 && p.g.nnz >= 0 && p.labels &&
             (int64_t)p.k * n < ((int64_t)1 << 31) && p.g.nnz < ((int64_t)1 << 31) - 1;
-  if (ok && n > 0)
-    ok = device_visible(p.g.row_ptr) && (p.g.nnz == 0 || device_visible(p.g.col)) &&
-         (!need_out || device_visible(p.out)) && (!p.init || device_visible(p.init)) &&
-         labels_ok(p.labels, p.k);
+  if (ok && n > 0) {
+    ok = vis.check(p.g.row_ptr) && (p.g.nnz == 0 || vis.check(p.g.col)) &&
+         (!need_out || vis.check(p.out)) && (!p.init || vis.check(p.init));
+    for (int i = 0; ok && i < p.k; ++i) ok = vis.check(p.labels[i]);
+  }
   return ok;
 }
 
@@ -1061,8 +1087,9 @@ int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stat
   // host-side argument checks, as mcc_consensus makes them
   std::vector<int32_t> eligible;
   std::vector<int32_t> fallback;
+  VisibleRanges vis;
   for (int32_t i = 0; i < count; ++i) {
-    if (!problem_ok(probs[i], true)) {
+    if (!problem_ok(probs[i], true, vis)) {
       status[i] = MCC_EINVAL;
       continue;
     }
@@ -1155,8 +1182,9 @@ int mcc_batch_tune(const mcc_problem* probs, int32_t count, const mcc_batch_opts
   memset(table, 0, sizeof *table);
   table->wg_per_cu = 2;
   std::vector<int32_t> ids;
+  VisibleRanges vis;
   for (int32_t i = 0; i < count; ++i) {
-    if (!problem_ok(probs[i], false)) return MCC_EINVAL;
+    if (!problem_ok(probs[i], false, vis)) return MCC_EINVAL;
     if (probs[i].k <= 256 && probs[i].g.n > 0) ids.push_back(i);
   }
   hipStream_t st = opts ? (hipStream_t)opts->stream : nullptr;
