@@ -691,23 +691,30 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) / 64;
   int64_t dn2 = 0, ds2 = 0;
   int32_t claimed = 0;
+  // the wave serves the proposals of its 64 vertices four at a time, one
+  // per group of 16 lanes, the lanes of a group spread over the partitions
+  constexpr int kApplyLanes = 16;
+  const int grp = lane / kApplyLanes, gl = lane % kApplyLanes;
   for (int64_t v0 = wave * 64; v0 < a.n; v0 += nwaves * 64) {
     const int64_t v = v0 + lane;
     const int32_t p = v < a.n ? a.prop[v] : kNone;
     uint64_t mask = __ballot(p >= 0);
     while (mask) {
-      const int b = __ffsll((unsigned long long)mask) - 1;
-      mask &= mask - 1;
+      uint64_t m = mask;  // this group's proposal: the grp-th selected vertex
+      for (int q = 0; q < grp; ++q) m &= m - 1;
+      const int b = m ? __ffsll((unsigned long long)m) - 1 : -1;
+      for (int q = 0; q < 64 / kApplyLanes; ++q) mask &= mask - 1;
+      const int32_t to = __shfl(p, b < 0 ? 0 : b, 64);
+      if (b < 0) continue;
       const int64_t w = v0 + b;
-      const int32_t to = __shfl(p, b, 64);
       const int32_t from = a.C[w];
       const int32_t* row = a.Lvm + w * a.k;
-      for (int i = lane; i < a.k; i += 64) {
+      for (int i = gl; i < a.k; i += kApplyLanes) {
         const int32_t l = row[i];
         agg_add(hkey, hval, a, cell_upd(a.t, i, to, l, claimed), +1, &dn2, &ds2);
         agg_add(hkey, hval, a, cell_upd(a.t, i, from, l, claimed), -1, &dn2, &ds2);
       }
-      if (lane == 0) {
+      if (gl == 0) {
         agg_add(hkey, hval, a, a.cells + to, +1, &dn2, &ds2);
         agg_add(hkey, hval, a, a.cells + from, -1, &dn2, &ds2);
       }
