@@ -17,6 +17,7 @@ namespace mcc {
 namespace {
 
 constexpr int kBatchMaxK = 256;
+constexpr int kBatchLds = 8192;  // int32 histogram entries in LDS (32 KiB)
 constexpr int32_t kNone = -1;
 constexpr int64_t kGainBias = (int64_t)1 << 33;
 
@@ -184,10 +185,10 @@ __device__ __attribute__((noinline)) void score_pass(const BatchInst& in, bool l
 __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
   __shared__ int64_t s_toff[kBatchMaxK + 1];
   __shared__ int32_t s_L[kBatchMaxK];
+  __shared__ int32_t s_h[kBatchLds];  // label counts, then one table slice
   __shared__ int32_t s_r32[kBlock / 64];
   __shared__ int64_t s_r64[kBlock / 64];
   __shared__ int32_t s_idx;
-  __shared__ int32_t s_flag;
   const int t = threadIdx.x;
   // workspace slot of this workgroup
   const int64_t slot = blockIdx.x;
@@ -267,9 +268,33 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
       }
     }
     __syncthreads();
-    // ---- labels: dense ids per partition, vertex-major rows ----
+    // ---- sizes, then labels and contingency table partition by partition ----
+    // Each partition's label counts and its K0 x L_i slice of the table are
+    // histogrammed in LDS when they fit and written once (no zero fill, no
+    // global atomics); the objective's sums of squares come from the same
+    // counts: O = k sum_x s_x^2 + sum_i sum_l |P_il|^2 - 2 sum N^2.
+    const bool lds_sizes = K0 <= kBatchLds;
+    for (int64_t x = t; x < K0; x += kBlock) {
+      owner[x] = ~0ull;
+      if (lds_sizes) s_h[x] = 0;
+      else s[x] = 0;
+    }
+    __syncthreads();
+    for (int64_t v = t; v < n; v += kBlock) {
+      if (lds_sizes) atomicAdd(&s_h[C[v]], 1);
+      else atomicAdd(&s[C[v]], 1);
+    }
+    __syncthreads();
+    int64_t acc = 0;
+    for (int64_t x = t; x < K0; x += kBlock) {
+      const int32_t sx = lds_sizes ? s_h[x] : s[x];
+      if (lds_sizes) s[x] = sx;
+      acc += (int64_t)k * sx * sx;
+    }
+    __syncthreads();
     int32_t status = 0;
-    for (int i = 0; i < k && !status; ++i) {
+    int64_t toff = 0;  // same in every thread
+    for (int i = 0; i < k && status != kBatchInvalid; ++i) {
       const int32_t* p = in.labels[i];
       int32_t m = -1, lo = 0;
       for (int64_t v = t; v < n; v += kBlock) {
@@ -287,18 +312,58 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
         status = kBatchTooBig;
         break;
       }
-      for (int64_t x = t; x <= m; x += kBlock) flags[x] = 0;
-      __syncthreads();
-      for (int64_t v = t; v < n; v += kBlock) {
-        const int32_t x = p[v];
-        if (!flags[x]) flags[x] = 1;
+      // label sizes |P_il| (in LDS when the label values fit), then ids
+      const bool lds_lab = (int64_t)m + 1 <= kBatchLds;
+      for (int64_t x = t; x <= m; x += kBlock) {
+        if (lds_lab) s_h[x] = 0;
+        else flags[x] = 0;
       }
       __syncthreads();
-      const int32_t Li = wg_scan(flags, (int64_t)m + 1);
-      if (t == 0) s_L[i] = Li;
+      for (int64_t v = t; v < n; v += kBlock) {
+        if (lds_lab) atomicAdd(&s_h[p[v]], 1);
+        else atomicAdd(&flags[p[v]], 1);
+      }
+      __syncthreads();
+      for (int64_t x = t; x <= m; x += kBlock) {
+        const int32_t c = lds_lab ? s_h[x] : flags[x];
+        acc += (int64_t)c * c;
+        flags[x] = c > 0;
+      }
+      __syncthreads();
+      const int32_t Li = wg_scan(flags, (int64_t)m + 1);  // flags: dense label ids
+      if (t == 0) {
+        s_L[i] = Li;
+        s_toff[i] = toff;
+      }
+      const int64_t entries = (int64_t)K0 * Li;
+      const bool fits = status == 0 && toff + entries <= w.cells_cap;
+      if (!fits) status = kBatchTooBig;  // keep counting: the size is reported
       for (int64_t v = t; v < n; v += kBlock) Lvm[v * k + i] = flags[p[v]];
+      if (fits) {
+        int32_t* Ni = N + toff;
+        const bool lds_tab = entries <= kBatchLds;
+        for (int64_t j = t; j < entries; j += kBlock) {
+          if (lds_tab) s_h[j] = 0;
+          else Ni[j] = 0;
+        }
+        __syncthreads();
+        for (int64_t v = t; v < n; v += kBlock) {
+          const int64_t cell = (int64_t)C[v] * Li + flags[p[v]];
+          if (lds_tab) atomicAdd(&s_h[cell], 1);
+          else atomicAdd(&Ni[cell], 1);
+        }
+        __syncthreads();
+        for (int64_t j = t; j < entries; j += kBlock) {
+          const int32_t c = lds_tab ? s_h[j] : Ni[j];
+          if (lds_tab) Ni[j] = c;
+          acc -= 2 * (int64_t)c * c;
+        }
+      }
+      toff += entries;
       __syncthreads();
     }
+    if (t == 0) s_toff[k] = toff;
+    res.cells = toff;
     if (status) {
       if (t == 0) {
         res.status = status;
@@ -307,45 +372,6 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
       __syncthreads();
       continue;
     }
-    if (t == 0) {
-      s_toff[0] = 0;
-      for (int i = 0; i < k; ++i) s_toff[i + 1] = s_toff[i] + (int64_t)K0 * s_L[i];
-      s_flag = s_toff[k] > w.cells_cap;
-    }
-    __syncthreads();
-    res.cells = s_toff[k];
-    if (s_flag) {
-      if (t == 0) {
-        res.status = kBatchTooBig;
-        report(res);
-      }
-      __syncthreads();
-      continue;
-    }
-    const int64_t cells = s_toff[k];
-    // ---- tables, sizes, objective ----
-    for (int64_t j = t; j < cells; j += kBlock) N[j] = 0;
-    for (int64_t x = t; x < K0; x += kBlock) {
-      s[x] = 0;
-      owner[x] = ~0ull;
-    }
-    __syncthreads();
-    for (int64_t v = t; v < n; v += kBlock) {
-      const int32_t c = C[v];
-      const int32_t* row = Lvm + v * k;
-      for (int i = 0; i < k; ++i) atomicAdd(&N[s_toff[i] + (int64_t)c * s_L[i] + row[i]], 1);
-      atomicAdd(&s[c], 1);
-    }
-    __syncthreads();
-    int64_t acc = 0;
-    for (int64_t x = t; x < K0; x += kBlock) acc += (int64_t)k * s[x] * s[x];
-    for (int64_t j = t; j < cells; j += kBlock) acc -= 2 * (int64_t)N[j] * N[j];
-    for (int i = 0; i < k; ++i)
-      for (int64_t l = t; l < s_L[i]; l += kBlock) {
-        int64_t h = 0;
-        for (int32_t x = 0; x < K0; ++x) h += N[s_toff[i] + (int64_t)x * s_L[i] + l];
-        acc += h * h;
-      }
     int64_t O = wg_reduce(acc, Add64(), s_r64);
     res.objective_init = O;
 
