@@ -81,14 +81,14 @@ __device__ int32_t wg_scan(int32_t* a, int64_t len) {
 
 // Apply (sign d) the move of v from `from` to `to` to sizes and counts;
 // returns the change of the sums of squares (N part in *dn2, sizes in *ds2).
-__device__ inline void bmove(int32_t* N, int32_t* s, const int32_t* Lvm, const int64_t* toff,
-                             const int32_t* L, int32_t k, int64_t v, int32_t from, int32_t to,
-                             int32_t d, int64_t* dn2, int64_t* ds2) {
+__device__ inline void bmove(int32_t* N, int32_t* s, const int32_t* Lvm, int32_t Lmax,
+                             int32_t k, int64_t v, int32_t from, int32_t to, int32_t d,
+                             int64_t* dn2, int64_t* ds2) {
   const int32_t* row = Lvm + v * k;
   for (int i = 0; i < k; ++i) {
     const int32_t l = row[i];
-    const int32_t o1 = atomicAdd(&N[toff[i] + (int64_t)to * L[i] + l], d);
-    const int32_t o2 = atomicAdd(&N[toff[i] + (int64_t)from * L[i] + l], -d);
+    const int32_t o1 = atomicAdd(&N[((int64_t)to * Lmax + l) * k + i], d);
+    const int32_t o2 = atomicAdd(&N[((int64_t)from * Lmax + l) * k + i], -d);
     *dn2 += 2 * (int64_t)o1 * d + 1 - 2 * (int64_t)o2 * d + 1;
   }
   const int32_t o1 = atomicAdd(&s[to], d);
@@ -104,7 +104,7 @@ __device__ inline void bmove(int32_t* N, int32_t* s, const int32_t* Lvm, const i
 template <int G>
 __device__ __attribute__((noinline)) void score_pass(const BatchInst& in, bool literal, const int32_t* C,
                            const int32_t* Lvm, const int32_t* N, const int32_t* s,
-                           const int64_t* s_toff, const int32_t* s_L, int32_t* prop,
+                           int32_t Lmax, int32_t* prop,
                            int64_t* dprop, int64_t* evals_out, int32_t* np_out) {
   constexpr int R = 8;  // arc registers per lane before re-reading memory
   constexpr int32_t kInf = 0x7fffffff;
@@ -133,7 +133,8 @@ __device__ __attribute__((noinline)) void score_pass(const BatchInst& in, bool l
     const int32_t* row = Lvm + v * k;
     auto agree = [&](int32_t y) -> int32_t {
       int32_t sum = 0;
-      for (int i = lane; i < k; i += G) sum += N[s_toff[i] + (int64_t)y * s_L[i] + row[i]];
+      const int64_t base = (int64_t)y * Lmax;
+      for (int i = lane; i < k; i += G) sum += N[(base + row[i]) * k + i];
       return group_sum<G>(sum);
     };
     int32_t last = -1, ncand = 0, bestx = kNone;
@@ -183,7 +184,6 @@ __device__ __attribute__((noinline)) void score_pass(const BatchInst& in, bool l
 }
 
 __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
-  __shared__ int64_t s_toff[kBatchMaxK + 1];
   __shared__ int32_t s_L[kBatchMaxK];
   __shared__ int32_t s_h[kBatchLds];  // label counts, then one table slice
   __shared__ int32_t s_r32[kBlock / 64];
@@ -292,9 +292,10 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
       acc += (int64_t)k * sx * sx;
     }
     __syncthreads();
+    // labels: dense ids per partition (vertex-major rows) and |P_il|
     int32_t status = 0;
-    int64_t toff = 0;  // same in every thread
-    for (int i = 0; i < k && status != kBatchInvalid; ++i) {
+    int32_t Lmax = 1;  // same in every thread
+    for (int i = 0; i < k; ++i) {
       const int32_t* p = in.labels[i];
       int32_t m = -1, lo = 0;
       for (int64_t v = t; v < n; v += kBlock) {
@@ -331,39 +332,17 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
       }
       __syncthreads();
       const int32_t Li = wg_scan(flags, (int64_t)m + 1);  // flags: dense label ids
-      if (t == 0) {
-        s_L[i] = Li;
-        s_toff[i] = toff;
-      }
-      const int64_t entries = (int64_t)K0 * Li;
-      const bool fits = status == 0 && toff + entries <= w.cells_cap;
-      if (!fits) status = kBatchTooBig;  // keep counting: the size is reported
+      if (t == 0) s_L[i] = Li;
+      Lmax = max(Lmax, Li);
       for (int64_t v = t; v < n; v += kBlock) Lvm[v * k + i] = flags[p[v]];
-      if (fits) {
-        int32_t* Ni = N + toff;
-        const bool lds_tab = entries <= kBatchLds;
-        for (int64_t j = t; j < entries; j += kBlock) {
-          if (lds_tab) s_h[j] = 0;
-          else Ni[j] = 0;
-        }
-        __syncthreads();
-        for (int64_t v = t; v < n; v += kBlock) {
-          const int64_t cell = (int64_t)C[v] * Li + flags[p[v]];
-          if (lds_tab) atomicAdd(&s_h[cell], 1);
-          else atomicAdd(&Ni[cell], 1);
-        }
-        __syncthreads();
-        for (int64_t j = t; j < entries; j += kBlock) {
-          const int32_t c = lds_tab ? s_h[j] : Ni[j];
-          if (lds_tab) Ni[j] = c;
-          acc -= 2 * (int64_t)c * c;
-        }
-      }
-      toff += entries;
       __syncthreads();
     }
-    if (t == 0) s_toff[k] = toff;
-    res.cells = toff;
+    // interleaved table N[(x * Lmax + l) * k + i]: the k counts one probe of
+    // a vertex needs lie side by side when its labels line up with its
+    // cluster (any injective relabelling leaves the counts unchanged)
+    const int64_t cells = (int64_t)K0 * Lmax * k;
+    res.cells = cells;
+    if (!status && cells > w.cells_cap) status = kBatchTooBig;
     if (status) {
       if (t == 0) {
         res.status = status;
@@ -371,6 +350,36 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
       }
       __syncthreads();
       continue;
+    }
+    // one partition at a time: its K0 x L_i counts histogrammed in LDS when
+    // they fit, written once; the sum of squares from the same counts
+    for (int i = 0; i < k; ++i) {
+      const int32_t Li = s_L[i];
+      const int64_t entries = (int64_t)K0 * Li;
+      const bool lds_tab = entries <= kBatchLds;
+      for (int64_t j = t; j < entries; j += kBlock) {
+        if (lds_tab) {
+          s_h[j] = 0;
+        } else {
+          const int64_t x = j / Li;
+          N[(x * Lmax + (j - x * Li)) * k + i] = 0;
+        }
+      }
+      __syncthreads();
+      for (int64_t v = t; v < n; v += kBlock) {
+        const int32_t c = C[v], l = Lvm[v * k + i];
+        if (lds_tab) atomicAdd(&s_h[(int64_t)c * Li + l], 1);
+        else atomicAdd(&N[((int64_t)c * Lmax + l) * k + i], 1);
+      }
+      __syncthreads();
+      for (int64_t j = t; j < entries; j += kBlock) {
+        const int64_t x = j / Li;
+        const int64_t cell = (x * Lmax + (j - x * Li)) * k + i;
+        const int32_t c = lds_tab ? s_h[j] : N[cell];
+        if (lds_tab) N[cell] = c;
+        acc -= 2 * (int64_t)c * c;
+      }
+      __syncthreads();
     }
     int64_t O = wg_reduce(acc, Add64(), s_r64);
     res.objective_init = O;
@@ -381,11 +390,11 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
       int32_t np = 0;
       const bool lit = b.literal != 0;
       switch (in.lanes) {
-        case 4: score_pass<4>(in, lit, C, Lvm, N, s, s_toff, s_L, prop, dprop, &evals, &np); break;
-        case 8: score_pass<8>(in, lit, C, Lvm, N, s, s_toff, s_L, prop, dprop, &evals, &np); break;
-        case 32: score_pass<32>(in, lit, C, Lvm, N, s, s_toff, s_L, prop, dprop, &evals, &np); break;
-        case 64: score_pass<64>(in, lit, C, Lvm, N, s, s_toff, s_L, prop, dprop, &evals, &np); break;
-        default: score_pass<16>(in, lit, C, Lvm, N, s, s_toff, s_L, prop, dprop, &evals, &np); break;
+        case 4: score_pass<4>(in, lit, C, Lvm, N, s, Lmax, prop, dprop, &evals, &np); break;
+        case 8: score_pass<8>(in, lit, C, Lvm, N, s, Lmax, prop, dprop, &evals, &np); break;
+        case 32: score_pass<32>(in, lit, C, Lvm, N, s, Lmax, prop, dprop, &evals, &np); break;
+        case 64: score_pass<64>(in, lit, C, Lvm, N, s, Lmax, prop, dprop, &evals, &np); break;
+        default: score_pass<16>(in, lit, C, Lvm, N, s, Lmax, prop, dprop, &evals, &np); break;
       }
       evals = wg_reduce(evals, Add64(), s_r64);
       const int64_t nprop = wg_reduce((int64_t)np, Add64(), s_r64);
@@ -399,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
       int64_t dn2 = 0, ds2 = 0;
       for (int64_t v = t; v < n; v += kBlock) {
         const int32_t to = prop[v];
-        if (to >= 0) bmove(N, s, Lvm, s_toff, s_L, k, v, C[v], to, +1, &dn2, &ds2);
+        if (to >= 0) bmove(N, s, Lvm, Lmax, k, v, C[v], to, +1, &dn2, &ds2);
       }
       dn2 = wg_reduce(dn2, Add64(), s_r64);
       ds2 = wg_reduce(ds2, Add64(), s_r64);
@@ -416,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
           const int32_t to = prop[v];
           if (to < 0) continue;
           const int32_t from = C[v];
-          bmove(N, s, Lvm, s_toff, s_L, k, v, from, to, -1, &junk, &junk);
+          bmove(N, s, Lvm, Lmax, k, v, from, to, -1, &junk, &junk);
           const uint64_t key = owner_key(dprop[v], v);
           atomicMin((unsigned long long*)&owner[from], (unsigned long long)key);
           atomicMin((unsigned long long*)&owner[to], (unsigned long long)key);
@@ -429,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_batch(BatchArgs b) {
           const int32_t from = C[v];
           const uint64_t key = owner_key(dprop[v], v);
           if (owner[from] == key && owner[to] == key) {
-            bmove(N, s, Lvm, s_toff, s_L, k, v, from, to, +1, &fn2, &fs2);
+            bmove(N, s, Lvm, Lmax, k, v, from, to, +1, &fn2, &fs2);
             ++com;
           } else {
             prop[v] = -2 - to;
