@@ -198,6 +198,102 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
       return group_sum<G>(sum);
     };
 
+    if constexpr (LIST && G == 64) {
+      if (fits && kfits) {
+        // a deferred vertex: its candidate clusters collected in increasing
+        // id (lane j holds candidates j and 64 + j), then its own cluster and
+        // the candidates scored four at a time by 16-lane groups, and the
+        // smallest (gain, cluster id) taken by a wave reduction
+        int32_t cand_lo = kInf, cand_hi = kInf, nc = 0;
+        for (;;) {
+          int32_t m = kInf;
+#pragma unroll
+          for (int r = 0; r < R; ++r) m = min(m, x[r]);
+          m = group_min<64>(m);
+          if (m == kInf) break;
+          if (lane == nc) cand_lo = m;
+          else if (lane == nc - 64) cand_hi = m;
+          ++nc;
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (x[r] == m) x[r] = kInf;
+        }
+        if (nc == 0) {
+          if (lane == 0) a.prop[v] = kNone;
+          continue;
+        }
+        const int sg = lane >> 4, sl = lane & 15;
+        int32_t lb[4];  // labels of partitions sl + 16 q
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lb[q] = sl + 16 * q < k ? row[sl + 16 * q] : 0;
+        int32_t s_lo = 0, s_hi = 0, s_v = 0;
+        const int nitems = nc + 1;  // item 0: the own cluster; item c + 1: candidate c
+        for (int j0 = 0; j0 < nitems; j0 += 4) {
+          const int it = j0 + sg, ci = it - 1;
+          const int32_t y_lo = __shfl(cand_lo, ci < 0 ? 0 : (ci & 63), 64);
+          const int32_t y_hi = __shfl(cand_hi, ci < 0 ? 0 : (ci & 63), 64);
+          const int32_t y = it == 0 ? cv : (ci < 64 ? y_lo : y_hi);
+          int32_t sum = 0;
+          if (it < nitems) {
+            if (a.members && a.s[y] <= kMemberSumMax) {
+              const int32_t cnt = a.s[y];  // <= 16: one member id per lane
+              const int32_t mid = sl < cnt ? a.members[a.mstart[y] + sl] : 0;
+              for (int32_t mm = 0; mm < cnt; ++mm) {
+                const int32_t* ru = a.Lvm + (int64_t)__shfl(mid, mm, 16) * k;
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                  if (sl + 16 * q < k) sum += ru[sl + 16 * q] == lb[q];
+              }
+            } else {
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                if (sl + 16 * q < k) sum += count_of(a.t, sl + 16 * q, y, lb[q]);
+            }
+          }
+          sum = group_sum<16>(sum);
+          if (j0 == 0) s_v = __shfl(sum, 0, 64);
+          const int g_lo = lane + 1 - j0, g_hi = lane + 65 - j0;  // groups holding my items
+          const int32_t got_lo = __shfl(sum, (g_lo >= 0 && g_lo < 4) ? g_lo * 16 : 0, 64);
+          const int32_t got_hi = __shfl(sum, (g_hi >= 0 && g_hi < 4) ? g_hi * 16 : 0, 64);
+          if (g_lo >= 0 && g_lo < 4) s_lo = got_lo;
+          if (g_hi >= 0 && g_hi < 4) s_hi = got_hi;
+        }
+        const int64_t scv = a.s[cv];
+        int64_t bd = INT64_MAX;
+        int32_t bx = kInf;
+        auto consider = [&](int32_t xc, int32_t sx) {
+          int64_t d = 2 * ((int64_t)s_v - sx) + (int64_t)k * ((int64_t)a.s[xc] - scv - 1);
+          if (a.literal) d += k;
+          if (d < bd || (d == bd && xc < bx)) {
+            bd = d;
+            bx = xc;
+          }
+        };
+        if (lane < nc) consider(cand_lo, s_lo);
+        if (lane + 64 < nc) consider(cand_hi, s_hi);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const int64_t od = __shfl_xor(bd, o, 64);
+          const int32_t ox = __shfl_xor(bx, o, 64);
+          if (od < bd || (od == bd && ox < bx)) {
+            bd = od;
+            bx = ox;
+          }
+        }
+        if (lane == 0) {
+          evals += nc;
+          boundary += 1;
+          const bool p = bd < 0;
+          a.prop[v] = p ? bx : kNone;
+          if (p) {
+            a.dprop[v] = bd;
+            ++nprop;
+          }
+        }
+        continue;
+      }
+    }
+
     int32_t last = -1, ncand = 0, bestx = kNone;
     int64_t bestd = 0, s_own = -1;
     const int64_t sc = a.s[cv];
