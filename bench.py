@@ -90,7 +90,6 @@ def bench_batch(args):
     D = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     probs = [{"row_ptr": D(i.row_ptr), "col": D(i.col), "labels": D(i.labels), "init": D(i.init)}
              for i in insts]
-    outs = [torch.empty(i.n, dtype=torch.int32, device="cuda") for i in insts]
     torch.cuda.synchronize()
     table, tune_s, untuned = None, 0.0, None
     if args.tune and args.lanes == 0:
@@ -100,24 +99,30 @@ def bench_batch(args):
         table = mcc.batch_tune(probs)
         tune_s = time.perf_counter() - t0
         log(f"tuned on {len(probs)} instances in {tune_s:.1f} s: {table.as_dict()}")
-        mcc.consensus_batch(probs, outs=outs)
+        pb0 = mcc.pack_batch(insts)
+        mcc.consensus_batch_packed(pb0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            mcc.consensus_batch(probs, outs=outs)
+            mcc.consensus_batch_packed(pb0)
         torch.cuda.synchronize()
         untuned = (time.perf_counter() - t0) / args.steps
-    kw = dict(outs=outs, wg_per_cu=args.wg_per_cu, lanes=args.lanes, tune=table)
+        del pb0
+    # the timed calls take the instances packed on the device (concatenated
+    # CSR, labels and outputs with per-instance offsets), packed once here
+    pb = mcc.pack_batch(insts)
+    kw = dict(wg_per_cu=args.wg_per_cu, lanes=args.lanes, tune=table)
     for _ in range(args.warmup):
-        mcc.consensus_batch(probs, **kw)
+        mcc.consensus_batch_packed(pb, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        _, stats, codes, info = mcc.consensus_batch(probs, **kw)
+        info = mcc.consensus_batch_packed(pb, **kw)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / args.steps
-    assert all(c == 0 for c in codes)
-    batch_out = [o.cpu().numpy() for o in outs]
+    assert info["rc"] == 0 and all(pb.status[j] == 0 for j in range(count))
+    stats = [pb.stats[j].as_dict() for j in range(count)]
+    batch_out = [pb.output(j).cpu().numpy() for j in range(count)]
     # one at a time, same instances, once
     t0 = time.perf_counter()
     same = True

@@ -425,3 +425,98 @@ def consensus_groups(row_ptr, col, labels, lam=-1, init="first", max_rounds=0, f
 def release_workspace():
     """Free the device workspace the library keeps between calls."""
     _check(lib().mcc_release_workspace())
+
+
+# ---------------------------------------------------------------------------
+# packed batches: many instances in a few concatenated device tensors
+# ---------------------------------------------------------------------------
+_PROBLEM_DTYPE = None
+
+
+def _problem_dtype():
+    """numpy record with the memory layout of mcc_problem (and of Problem)."""
+    global _PROBLEM_DTYPE
+    if _PROBLEM_DTYPE is None:
+        import numpy as np
+        _PROBLEM_DTYPE = np.dtype({
+            "names": ["n", "nnz", "row_ptr", "col", "labels", "k", "init", "out"],
+            "formats": ["<i8", "<i8", "<u8", "<u8", "<u8", "<i4", "<u8", "<u8"],
+            "offsets": [Csr.n.offset, Csr.nnz.offset, Csr.row_ptr.offset, Csr.col.offset,
+                        Problem.labels.offset, Problem.k.offset, Problem.init.offset,
+                        Problem.out.offset],
+            "itemsize": ctypes.sizeof(Problem)})
+    return _PROBLEM_DTYPE
+
+
+class PackedBatch:
+    """Instances concatenated on the device: row offsets, arcs, labels
+    (each instance's k x n block, row-major), initial clusters and outputs,
+    with per-instance offsets; the mcc_problem records that point into them
+    are built once, with array arithmetic.  Build with pack_batch."""
+
+    def __init__(self, row_ptr, col, labels, init, out, n, nnz, k, rp_off, col_off, lab_off,
+                 has_init):
+        import numpy as np
+        self.row_ptr, self.col, self.labels, self.init, self.out = row_ptr, col, labels, init, out
+        self.n, self.nnz, self.k = n, nnz, k
+        self.count = int(n.size)
+        self.v_off = np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+        # host array of all label row pointers: instance j, partition i
+        kcum = np.concatenate([[0], np.cumsum(k)]).astype(np.int64)
+        inst = np.repeat(np.arange(self.count), k)
+        part = np.arange(int(kcum[-1])) - kcum[inst]
+        self.label_rows = (labels.data_ptr() + 4 * (lab_off[inst] + part * n[inst])).astype(np.uint64)
+        rec = np.zeros(self.count, dtype=_problem_dtype())
+        rec["n"], rec["nnz"], rec["k"] = n, nnz, k
+        rec["row_ptr"] = row_ptr.data_ptr() + 8 * rp_off
+        rec["col"] = np.where(nnz > 0, col.data_ptr() + 4 * col_off, 0)
+        rec["labels"] = self.label_rows.ctypes.data + 8 * kcum[:-1]
+        rec["init"] = np.where(has_init, init.data_ptr() + 4 * self.v_off, 0)
+        rec["out"] = np.where(n > 0, out.data_ptr() + 4 * self.v_off, 0)
+        self.records = rec
+        self.stats = (Stats * max(1, self.count))()
+        self.status = (ctypes.c_int32 * max(1, self.count))()
+
+    def output(self, j):
+        """The output tensor of instance j (a view into the packed outputs)."""
+        o = int(self.v_off[j])
+        return self.out[o:o + int(self.n[j])]
+
+
+def pack_batch(instances, device="cuda"):
+    """Concatenate host instances (objects with numpy row_ptr int64 [n+1],
+    col int32, labels int32 [k, n] and init int32 [n] or None) into one
+    PackedBatch resident on the device."""
+    import numpy as np
+    import torch
+    n = np.array([i.row_ptr.size - 1 for i in instances], np.int64)
+    nnz = np.array([i.col.size for i in instances], np.int64)
+    k = np.array([i.labels.shape[0] for i in instances], np.int64)
+    rp_off = np.concatenate([[0], np.cumsum(n + 1)[:-1]]).astype(np.int64)
+    col_off = np.concatenate([[0], np.cumsum(nnz)[:-1]]).astype(np.int64)
+    lab_off = np.concatenate([[0], np.cumsum(n * k)[:-1]]).astype(np.int64)
+    has_init = np.array([i.init is not None for i in instances])
+    T = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a, dt)).to(device)
+    row_ptr = T(np.concatenate([i.row_ptr for i in instances]), np.int64)
+    col = T(np.concatenate([i.col for i in instances] + [np.zeros(1, np.int32)]), np.int32)
+    labels = T(np.concatenate([i.labels.reshape(-1) for i in instances] + [np.zeros(1, np.int32)]),
+               np.int32)
+    init = T(np.concatenate([i.init if i.init is not None else np.zeros(i.row_ptr.size - 1, np.int32)
+                             for i in instances] + [np.zeros(1, np.int32)]), np.int32)
+    out = torch.empty(int(n.sum()) + 1, dtype=torch.int32, device=device)
+    return PackedBatch(row_ptr, col, labels, init, out, n, nnz, k, rp_off, col_off, lab_off, has_init)
+
+
+def consensus_batch_packed(pb, *, max_rounds=0, flags=0, lanes=0, wg_per_cu=0, stream=None,
+                           tune=None, tune_cache_path=None):
+    """mcc_consensus_batch over a PackedBatch: outputs land in pb.out (see
+    pb.output(j)), per-instance stats in pb.stats, codes in pb.status.
+    Returns the batch call's info (instances finished in the persistent
+    kernel, wall time, return code)."""
+    o = _batch_opts(max_rounds, flags, lanes, wg_per_cu, stream, tune, tune_cache_path)
+    o.status = ctypes.cast(pb.status, ctypes.c_void_p)
+    recs = ctypes.cast(pb.records.ctypes.data, ctypes.POINTER(Problem))
+    rc = lib().mcc_consensus_batch(recs, pb.count, pb.stats, ctypes.byref(o))
+    if rc not in (0, MCC_EINVAL):
+        _check(rc)
+    return {"solved_in_batch": o.solved_in_batch, "ms_total": o.ms_total, "rc": rc}

@@ -147,3 +147,25 @@ def test_autotune_then_tuned_batch(mcc, tmp_path):
             if n > 0 and k <= 256 and st["lanes_used"]:
                 kc = 0 if k <= 8 else 1 if k <= 16 else 2 if k <= 32 else 3 if k <= 64 else 4
                 assert st["lanes_used"] == by_bucket[(max(n, 1).bit_length() - 1, kc)]
+
+
+def test_packed_batch_equals_batch(mcc):
+    # the same instances concatenated on the device with per-instance offsets
+    import types
+    import torch
+    print("[gpu-case] packed batch", flush=True)
+    items = instances()
+    hosts = [types.SimpleNamespace(row_ptr=i.row_ptr, col=i.col, labels=i.labels,
+                                   init=None if init is None else i.init) for i, init in items]
+    pb = mcc.pack_batch(hosts)
+    info = mcc.consensus_batch_packed(pb)
+    torch.cuda.synchronize()
+    assert info["rc"] == 0 and all(pb.status[j] == 0 for j in range(pb.count))
+    probs = [to_problem(i, init) for i, init in items]
+    outs, stats, codes, _ = mcc.consensus_batch(probs)
+    torch.cuda.synchronize()
+    for j in range(pb.count):
+        assert np.array_equal(pb.output(j).cpu().numpy(), outs[j].cpu().numpy())
+        got = pb.stats[j].as_dict()
+        for key in KEYS:
+            assert got[key] == stats[j][key], (j, key)
