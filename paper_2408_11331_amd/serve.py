@@ -104,19 +104,23 @@ class GpuBackend:
     def solve(self, reqs: List[Request], large: bool, stream) -> None:
         torch, mcc = self.torch, self.mcc
         with torch.cuda.stream(stream):
-            dev = [self._upload(r) for r in reqs]
             if large:
-                for r, d in zip(reqs, dev):
+                for r in reqs:
+                    d = self._upload(r)
                     out, st = mcc.consensus(d["row_ptr"], d["col"], d["labels"], d["init"],
                                             max_rounds=self.max_rounds, stream=stream)
                     r.out, r.stats = out.cpu().numpy(), st
             else:
-                outs, stats, codes, _ = mcc.consensus_batch(dev, max_rounds=self.max_rounds,
-                                                            stream=stream)
-                for r, o, st, c in zip(reqs, outs, stats, codes):
+                # the batch's requests concatenated in one upload
+                pb = mcc.pack_batch(reqs)
+                mcc.consensus_batch_packed(pb, max_rounds=self.max_rounds, stream=stream)
+                out = pb.out.cpu().numpy()
+                for j, r in enumerate(reqs):
+                    c = pb.status[j]
                     if c != 0:
                         r.error = mcc.lib().mcc_strerror(c).decode()
-                    r.out, r.stats = o.cpu().numpy(), st
+                    o = int(pb.v_off[j])
+                    r.out, r.stats = out[o:o + r.n], pb.stats[j].as_dict()
             stream.synchronize()
 
 
