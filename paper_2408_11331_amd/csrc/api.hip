@@ -409,7 +409,7 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
     t.hocc = hc;
     t.herr = hc + 1;
     launch_hash_clear(t, st);
-    launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, t, st);
+    launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, maxL, t, st);
     S->t = t;
     S->maxL = maxL;
     S->total = slots;
@@ -432,7 +432,7 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
   Tables bt = blocked_tables(ar, *S, S->lab.L, Lh, st, &total);
   const bool try_align = want_rows && K0 <= kAlignMaxClusters;
   const int64_t stride = try_align ? std::max<int64_t>(1, n / (1 << 18)) : 1;
-  launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, bt, st, stride);
+  launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, maxL, bt, st, stride);
   S->t = bt;
   S->maxL = maxL;
   S->total = total;
@@ -469,7 +469,7 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
       it.Lmax = Lmax;
       it.k = k;
       it.interleaved = 1;
-      launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, it, st);
+      launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, Lmax, it, st);
       S->t = it;
       S->maxL = Lmax;
       S->total = cells;
@@ -478,7 +478,7 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
   }
   if (try_align && !aligned && stride > 1) {  // sampled blocked tables: count them all
     launch_fill_i32(bt.N, total, 0, st);
-    launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, bt, st, 1);
+    launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, maxL, bt, st, 1);
   }
   if (want_rows) {
     S->Lvm = ar.get<int32_t>(n * k);

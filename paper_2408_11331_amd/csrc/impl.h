@@ -186,8 +186,9 @@ void launch_fill_i32(int32_t* a, int64_t n, int32_t v, hipStream_t st);
 void launch_fill_u64(uint64_t* a, int64_t n, uint64_t v, hipStream_t st);
 // Counts a sample of the vertices, runs of 64 consecutive vertices one run
 // in every `stride` (stride 1: all vertices, the exact tables).
+// max_l: the largest label id bound of the table's partitions.
 void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t* loff,
-                  const int32_t* fmap, int64_t n, int32_t k, int32_t K0, Tables t,
+                  const int32_t* fmap, int64_t n, int32_t k, int32_t K0, int32_t max_l, Tables t,
                   hipStream_t st, int64_t stride = 1);
 void launch_sizes(const int32_t* C, int64_t n, int32_t K0, int32_t* s, hipStream_t st);
 void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, const int32_t* s,

@@ -7,6 +7,8 @@
 // closed-form gain of a move needs; the paper instead sums over cluster
 // members (Methods, "Computation and memory complexity"), which costs
 // O(|cluster| k) per candidate where these tables cost O(k).
+#include <algorithm>
+
 #include "impl.h"
 
 namespace mcc {
@@ -225,23 +227,24 @@ constexpr int kLdsHist = 16384;  // int32 entries privatised in LDS (64 KiB)
 constexpr int64_t kSampleRun = 64;  // vertices per run of a sampled build
 
 // Workgroup (b, i) counts the pairs (C(v), P_i(v)) of its vertex range for
-// partition i.  When partition i's K0 x L[i] slice fits kLdsHist entries the
-// counts are gathered in LDS and flushed once; otherwise they go straight to
-// the global table.
+// partition i.  When partition i's K0 x L[i] slice fits the LDS the launch
+// sized (lds_cap entries, at most kLdsHist) the counts are gathered there and
+// flushed once; otherwise they go straight to the global table.
 __global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
                                                   const int32_t* const* __restrict__ labels,
                                                   const int64_t* __restrict__ loff,
                                                   const int32_t* __restrict__ fmap, int64_t n,
-                                                  int32_t K0, Tables t, int64_t stride) {
-  __shared__ int32_t h[kLdsHist];
+                                                  int32_t K0, Tables t, int64_t stride,
+                                                  int32_t lds_cap) {
+  extern __shared__ int32_t h[];  // lds_cap entries, sized by the launch
   const int i = blockIdx.y;
   const int32_t Li = t.L[i];
   const int64_t entries = (int64_t)K0 * Li;
-  const bool lds = !t.hashed && entries <= kLdsHist;
+  const bool lds = !t.hashed && entries > 0 && entries <= lds_cap;
   // Counts concentrate on few cells (a cluster's members mostly share their
   // labels), so threads spread over up to 8 copies of a small slice: fewer
   // atomics on one LDS word at a time.
-  const int copies = lds ? (int)min((int64_t)8, kLdsHist / max(entries, (int64_t)1)) : 1;
+  const int copies = lds ? (int)min((int64_t)8, lds_cap / max(entries, (int64_t)1)) : 1;
   int32_t* hc = h + (threadIdx.x % copies) * entries;
   if (lds) {
     for (int j = threadIdx.x; j < entries * copies; j += kBlock) h[j] = 0;
@@ -629,15 +632,24 @@ void launch_fill_u64(uint64_t* a, int64_t n, uint64_t v, hipStream_t st) {
 }
 
 void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t* loff,
-                  const int32_t* fmap, int64_t n, int32_t k, int32_t K0, Tables t,
+                  const int32_t* fmap, int64_t n, int32_t k, int32_t K0, int32_t max_l, Tables t,
                   hipStream_t st, int64_t stride) {
   // enough workgroups per partition to fill the chip, few enough that the
   // LDS flush stays small next to the counting
   int64_t per_part = ((n + stride - 1) / stride + 4095) / 4096;  // about the sample size
   if (per_part > 64) per_part = 64;
   if (per_part < 1) per_part = 1;
+  // LDS sized to the largest slice (up to 8 copies within 32 KiB; a slice
+  // of up to kLdsHist entries alone), so that more workgroups share a CU
+  const int64_t slice = (int64_t)K0 * max_l;
+  int32_t cap = 0;
+  if (!t.hashed && slice <= kLdsHist / 2)
+    cap = (int32_t)(slice * std::min<int64_t>(8, (kLdsHist / 2) / std::max<int64_t>(slice, 1)));
+  else if (!t.hashed && slice <= kLdsHist)
+    cap = kLdsHist;
   dim3 g((unsigned)per_part, k);
-  k_build<<<g, kBlock, 0, st>>>(C, dlabels, loff, fmap, n, K0, t, stride);
+  k_build<<<g, kBlock, (size_t)cap * sizeof(int32_t), st>>>(C, dlabels, loff, fmap, n, K0, t,
+                                                           stride, cap);
 }
 
 void launch_sizes(const int32_t* C, int64_t n, int32_t K0, int32_t* s, hipStream_t st) {
