@@ -92,17 +92,51 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(const int32_t* __restrict_
 }
 
 // ---- labels ----------------------------------------------------------------
+// Visits the labels p[0, n) of one partition, spread over the x dimension
+// of the grid: 16-byte loads over the aligned middle of the row, four of them
+// in flight per thread and handed to f16 as sixteen labels, single loads
+// for the unaligned head and the tail, handed to f.  Past the end of the
+// middle, loads are clamped to its last word instead of branched around, so
+// a label may be visited more than once: f and f16 must be idempotent.
+// Label rows are seen as global memory: their loads are global, not flat,
+// so that waits on scalar and LDS operations do not wait on them too.
+typedef __attribute__((address_space(1))) int32_t global_i32;
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) i32x4 global_i4;
+
+template <typename F, typename F16>
+__device__ inline void for_each_label(const int32_t* __restrict__ row, int64_t n, F&& f,
+                                      F16&& f16) {
+  const global_i32* __restrict__ p = (const global_i32*)row;
+  const int64_t head = min(n, (int64_t)(((16 - ((uintptr_t)p & 15)) & 15) >> 2));
+  const int64_t nv = (n - head) >> 2;  // 16-byte words
+  const int64_t tail = head + nv * 4;
+  const int64_t t = gtid(), T = gstride();
+  if (t < head) f(p[t]);
+  if (t < n - tail) f(p[tail + t]);
+  const global_i4* __restrict__ q = (const global_i4*)(p + head);
+  for (int64_t w = t; w < nv; w += 4 * T) {
+    const i32x4 a = q[w], b = q[min(w + T, nv - 1)], c = q[min(w + 2 * T, nv - 1)],
+                d = q[min(w + 3 * T, nv - 1)];
+    const int32_t x[16] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w,
+                           c.x, c.y, c.z, c.w, d.x, d.y, d.z, d.w};
+    f16(x);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_label_max(const int32_t* const* __restrict__ labels,
                                                       int64_t n, int32_t* __restrict__ maxlab,
                                                       int32_t* __restrict__ err) {
   __shared__ int32_t s_m[kBlock / 64], s_lo[kBlock / 64];
-  const int32_t* p = labels[blockIdx.y];
   int32_t m = -1, lo = 0;
-  for (int64_t v = gtid(); v < n; v += gstride()) {
-    const int32_t x = p[v];
+  auto f = [&](int32_t x) {
     m = max(m, x);
     lo = min(lo, x);
-  }
+  };
+  for_each_label(labels[blockIdx.y], n, f, [&](const int32_t(&x)[16]) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) f(x[j]);
+  });
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
     m = max(m, __shfl_xor(m, o, 64));
@@ -126,12 +160,19 @@ __global__ __launch_bounds__(kBlock) void k_label_max(const int32_t* const* __re
 __global__ __launch_bounds__(kBlock) void k_label_mark(const int32_t* const* __restrict__ labels,
                                                        int64_t n, const int64_t* __restrict__ loff,
                                                        int32_t* __restrict__ flags) {
-  const int32_t* p = labels[blockIdx.y];
   int32_t* f = flags + loff[blockIdx.y];
-  for (int64_t v = gtid(); v < n; v += gstride()) {
-    const int32_t x = p[v];
-    if (!f[x]) f[x] = 1;  // most labels repeat: skip the store when set
-  }
+  // most labels repeat: skip the store when the flag is set; sixteen flags
+  // are read before any is written (a label seen twice is written twice)
+  for_each_label(
+      labels[blockIdx.y], n, [&](int32_t x) { if (!f[x]) f[x] = 1; },
+      [&](const int32_t(&x)[16]) {
+        int32_t seen[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) seen[j] = f[x[j]];
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (!seen[j]) f[x[j]] = 1;
+      });
 }
 
 __global__ void k_label_counts(const int32_t* __restrict__ scan, const int64_t* __restrict__ loff,
@@ -165,23 +206,71 @@ __global__ __launch_bounds__(kBlock) void k_fmap_update(const int32_t* __restric
 
 // Label ids, transposed to vertex-major rows: Lvm[v * k + i] = id of
 // P_i(v).  A workgroup moves a tile of tv vertices x k partitions through
-// LDS so that both the partition-major reads and the row writes coalesce.
+// LDS: waves read 64-vertex pieces of partition rows (eight pieces in flight
+// per wave), then the workgroup writes the tile's rows * k outputs, which are
+// contiguous, in order.
 __global__ __launch_bounds__(kBlock) void k_label_transpose(
     const int32_t* const* __restrict__ labels, int32_t k, int64_t n,
     const int64_t* __restrict__ loff, const int32_t* __restrict__ fmap, int tv,
     int32_t* __restrict__ Lvm) {
-  extern __shared__ int32_t tile[];  // [k][tv + 1]
+  extern __shared__ int32_t tile[];  // [k][tv + 1], then one spare word
+  constexpr int kWaves = kBlock / 64, kInFlight = 8;
   const int64_t v0 = (int64_t)blockIdx.x * tv;
-  const int rows = min((int64_t)tv, n - v0);
-  for (int f = threadIdx.x; f < tv * k; f += kBlock) {
-    int vv = f % tv, i = f / tv;
-    if (vv < rows) tile[i * (tv + 1) + vv] = fmap[loff[i] + labels[i][v0 + vv]];
+  const int rows = (int)min((int64_t)tv, n - v0);
+  // the wave index through a scalar register, so that the partition of a
+  // piece, its row pointer and its label map offset are scalar loads
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cpr = (rows + 63) >> 6;  // 64-vertex pieces per partition row
+  const int items = k * cpr;
+  for (int b = wave; b < items; b += kInFlight * kWaves) {
+    // indexes clamped into the tile instead of branches, so that all the
+    // loads issue before the first wait (a clamped lane reloads a valid
+    // label and drops it)
+    int32_t x[kInFlight];
+#pragma unroll
+    for (int u = 0; u < kInFlight; ++u) {
+      const int it = min(b + u * kWaves, items - 1), i = it / cpr;
+      const global_i32* row = (const global_i32*)labels[i];
+      x[u] = row[v0 + min((it - i * cpr) * 64 + lane, rows - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < kInFlight; ++u) {
+      const int it = min(b + u * kWaves, items - 1), i = it / cpr;
+      x[u] = fmap[loff[i] + x[u]];
+    }
+    // a clamped lane writes the spare word past the tile
+#pragma unroll
+    for (int u = 0; u < kInFlight; ++u) {
+      const int it0 = b + u * kWaves, it = min(it0, items - 1), i = it / cpr;
+      const int vv = (it - i * cpr) * 64 + lane;
+      tile[it0 < items && vv < rows ? i * (tv + 1) + vv : k * (tv + 1)] = x[u];
+    }
   }
   __syncthreads();
   int32_t* dst = Lvm + v0 * k;
-  for (int f = threadIdx.x; f < rows * k; f += kBlock) {
-    int vv = f / k, i = f % k;
+  const int total = rows * k, sv = kBlock / k, si = kBlock - sv * k;
+  int vv = threadIdx.x / k, i = threadIdx.x - vv * k;
+  for (int f = threadIdx.x; f < total; f += kBlock) {
     dst[f] = tile[i * (tv + 1) + vv];
+    i += si;
+    vv += sv;
+    if (i >= k) {
+      i -= k;
+      ++vv;
+    }
+  }
+}
+
+// The same for a partition count too large for a useful LDS tile: each
+// thread writes one output, reading its label directly.
+__global__ __launch_bounds__(kBlock) void k_label_transpose_direct(
+    const int32_t* const* __restrict__ labels, int32_t k, int64_t n,
+    const int64_t* __restrict__ loff, const int32_t* __restrict__ fmap,
+    int32_t* __restrict__ Lvm) {
+  for (int64_t f = gtid(); f < n * k; f += gstride()) {
+    const int64_t v = f / k;
+    const int32_t i = (int32_t)(f - v * k);
+    Lvm[f] = fmap[loff[i] + labels[i][v]];
   }
 }
 
@@ -559,13 +648,14 @@ void launch_scan(const int32_t* in, int32_t* out, int64_t len, int32_t* tmp, hip
 
 void launch_label_max(const int32_t* const* dlabels, int32_t k, int64_t n, int32_t* maxlab,
                       int32_t* err, hipStream_t st) {
-  dim3 g(grid_for(n, kBlock, 256), k);
+  // few workgroups: one atomic each per partition
+  dim3 g(grid_for(n, kBlock * 16, 256), k);
   k_label_max<<<g, kBlock, 0, st>>>(dlabels, n, maxlab, err);
 }
 
 void launch_label_mark(const int32_t* const* dlabels, int32_t k, int64_t n, const int64_t* loff,
                        int32_t* flags, hipStream_t st) {
-  dim3 g(grid_for(n, kBlock, 256), k);
+  dim3 g(grid_for(n, kBlock * 16, 2048), k);  // sixteen labels a thread
   k_label_mark<<<g, kBlock, 0, st>>>(dlabels, n, loff, flags);
 }
 
@@ -602,9 +692,14 @@ void launch_align(const Tables& blocked, int32_t k, int32_t K0, int32_t maxL,
 void launch_label_transpose(const int32_t* const* dlabels, int32_t k, int64_t n,
                             const int64_t* loff, const int32_t* fmap, int32_t* Lvm,
                             hipStream_t st) {
-  int tv = 64;
-  while (tv > 1 && (int64_t)(tv + 1) * k * 4 > 48 * 1024) tv >>= 1;
-  size_t lds = (size_t)(tv + 1) * k * sizeof(int32_t);
+  int tv = 256;
+  while (tv > 16 && (int64_t)(tv + 1) * k * 4 + 4 > 32 * 1024) tv >>= 1;
+  if ((int64_t)(tv + 1) * k * 4 + 4 > 32 * 1024) {
+    k_label_transpose_direct<<<grid_for(n * k, kBlock, 8192), kBlock, 0, st>>>(dlabels, k, n,
+                                                                              loff, fmap, Lvm);
+    return;
+  }
+  size_t lds = ((size_t)(tv + 1) * k + 1) * sizeof(int32_t);
   int64_t nb = (n + tv - 1) / tv;
   k_label_transpose<<<(unsigned)nb, kBlock, lds, st>>>(dlabels, k, n, loff, fmap, tv, Lvm);
 }

@@ -120,6 +120,19 @@ def test_random_instances(mcc, seed, n, k, init):
         assert_same(g, o)
 
 
+@pytest.mark.parametrize("n,k", [(301, 600), (1000, 3), (517, 50), (5, 9)])
+def test_label_row_shapes(mcc, n, k):
+    # vertex-major label rows through their three layouts: many partitions
+    # (one output per thread), few partitions (256-vertex tiles, ragged
+    # last tile), 50 partitions (128-vertex tiles); odd n leaves partition
+    # rows off 16-byte alignment for the label scans
+    announce(f"label rows n={n} k={k}")
+    inst = synth.random_instance(n, k, avg_deg=6.0, n_labels=13, seed=n + k, init="random")
+    o = run_oracle(inst)
+    for flags in (0, mcc.MCC_F_HASH_TABLES):
+        assert_same(run_gpu(mcc, inst, flags=flags), o)
+
+
 @pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
 def test_high_degree_and_many_candidates(mcc, lanes):
     # hubs beyond the register budget and candidate sets larger than a group
