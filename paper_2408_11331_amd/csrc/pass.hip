@@ -738,24 +738,32 @@ __device__ inline int64_t move_counts(const PassArgs& a, int64_t v, int32_t from
 // ---------------------------------------------------------------------------
 // Apply every proposal with per-workgroup aggregation.  Updates are keyed by
 // table cell (sizes use keys cells + cluster) and summed in an LDS hash
-// before one global atomic per distinct key; a key that finds no free slot
-// within kHashProbe steps goes straight to the global counter.  A net
-// update d on a counter whose previous value is `old` changes its square by
-// 2 old d + d^2, so the flush measures the objective change exactly.
+// before one global atomic per distinct key.  Once half the slots hold keys
+// the table takes no new ones (probe runs stay short when a workgroup sees
+// many distinct keys, as on a first pass): a key not in it, or that finds no
+// free slot within kHashProbe steps, goes straight to the global counter.
+// A net update d on a counter whose previous value is `old` changes its
+// square by 2 old d + d^2, so the flush measures the objective change
+// exactly, whichever updates of a key went where.
 // ---------------------------------------------------------------------------
 constexpr int kHashSlots = 4096;
+constexpr int kHashOpen = kHashSlots / 2;  // keys the table takes
 constexpr int kHashProbe = 32;
 
-__device__ inline void agg_add(int32_t* hkey, int32_t* hval, const PassArgs& a, int64_t key,
-                               int32_t d, int64_t* dn2, int64_t* ds2) {
+__device__ inline void agg_add(int32_t* hkey, int32_t* hval, int32_t* fill, const PassArgs& a,
+                               int64_t key, int32_t d, int64_t* dn2, int64_t* ds2) {
   const int32_t k32 = (int32_t)key;
   uint32_t h = ((uint32_t)k32 * 2654435761u) >> 20;  // 12 bits: kHashSlots
 #pragma unroll 1
   for (int q = 0; q < kHashProbe; ++q) {
     int32_t cur = hkey[h];
     if (cur == -1) {
+      if (*fill >= kHashOpen) break;  // the key is not in the table
       cur = atomicCAS(&hkey[h], -1, k32);
-      if (cur == -1) cur = k32;
+      if (cur == -1) {
+        atomicAdd(fill, 1);
+        cur = k32;
+      }
     }
     if (cur == k32) {
       atomicAdd(&hval[h], d);
@@ -777,10 +785,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
   if (ctl->done) return;
   __shared__ int32_t hkey[kHashSlots];
   __shared__ int32_t hval[kHashSlots];
+  __shared__ int32_t fill;
   for (int j = threadIdx.x; j < kHashSlots; j += kBlock) {
     hkey[j] = -1;
     hval[j] = 0;
   }
+  if (threadIdx.x == 0) fill = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 64;
@@ -807,12 +817,12 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
       const int32_t* row = a.Lvm + w * a.k;
       for (int i = gl; i < a.k; i += kApplyLanes) {
         const int32_t l = row[i];
-        agg_add(hkey, hval, a, cell_upd(a.t, i, to, l, claimed), +1, &dn2, &ds2);
-        agg_add(hkey, hval, a, cell_upd(a.t, i, from, l, claimed), -1, &dn2, &ds2);
+        agg_add(hkey, hval, &fill, a, cell_upd(a.t, i, to, l, claimed), +1, &dn2, &ds2);
+        agg_add(hkey, hval, &fill, a, cell_upd(a.t, i, from, l, claimed), -1, &dn2, &ds2);
       }
       if (gl == 0) {
-        agg_add(hkey, hval, a, a.cells + to, +1, &dn2, &ds2);
-        agg_add(hkey, hval, a, a.cells + from, -1, &dn2, &ds2);
+        agg_add(hkey, hval, &fill, a, a.cells + to, +1, &dn2, &ds2);
+        agg_add(hkey, hval, &fill, a, a.cells + from, -1, &dn2, &ds2);
       }
     }
   }
