@@ -347,16 +347,34 @@ __global__ __launch_bounds__(kBlock) void k_build(const int32_t* __restrict__ C,
   const int64_t per = (ns + gridDim.x - 1) / gridDim.x;
   const int64_t j0 = (int64_t)blockIdx.x * per;
   const int64_t j1 = min(ns, j0 + per);
-  // partition-major input labels (coalesced when stride is 1) mapped to their ids
-  const int32_t* p = labels[i];
+  // partition-major input labels (coalesced when stride is 1) mapped to their
+  // ids, kBuildUnroll vertices a thread at a time: all their loads, then all
+  // the label map gathers, then the counts (a lane past the end reloads
+  // vertex 0 and counts nothing)
+  const global_i32* p = (const global_i32*)labels[i];
   const int32_t* map = fmap + loff[i];
   int32_t claimed = 0;
-  for (int64_t j = j0 + threadIdx.x; j < j1; j += kBlock) {
-    const int64_t v = (j / kSampleRun) * (kSampleRun * stride) + j % kSampleRun;
-    if (v >= n) continue;
-    const int32_t x = C[v], l = map[p[v]];
-    if (lds) atomicAdd(&hc[x * Li + l], 1);
-    else atomicAdd(counter(t, cell_upd(t, i, x, l, claimed)), 1);
+  constexpr int kBuildUnroll = 8;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += kBuildUnroll * kBlock) {
+    int32_t x[kBuildUnroll], l[kBuildUnroll];
+    bool ok[kBuildUnroll];
+#pragma unroll
+    for (int u = 0; u < kBuildUnroll; ++u) {
+      const int64_t jj = j + u * kBlock;
+      const int64_t v = (jj / kSampleRun) * (kSampleRun * stride) + jj % kSampleRun;
+      ok[u] = jj < j1 && v < n;
+      const int64_t vc = ok[u] ? v : 0;
+      x[u] = C[vc];
+      l[u] = p[vc];
+    }
+#pragma unroll
+    for (int u = 0; u < kBuildUnroll; ++u) l[u] = map[l[u]];
+#pragma unroll
+    for (int u = 0; u < kBuildUnroll; ++u) {
+      if (!ok[u]) continue;
+      if (lds) atomicAdd(&hc[x[u] * Li + l[u]], 1);
+      else atomicAdd(counter(t, cell_upd(t, i, x[u], l[u], claimed)), 1);
+    }
   }
   if (t.hashed) flush_claims(t, claimed);
   if (lds) {
