@@ -276,8 +276,9 @@ def main():
                     help="run a 512 MiB elementwise copy first (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              f"(the multi-GPU sharding is a design, not code)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library "
+              f"solves on one device (sharding over several GPUs is described, not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
