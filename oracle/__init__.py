@@ -67,13 +67,15 @@ def lib():
         L.mccref_delta.argtypes = [p, p, i32, i64, i64, i32, p]
         L.mccref_score.argtypes = [p, p, i64, p, i32, p, i64, i64, i32, p, p, p]
         L.mccref_consensus.argtypes = [p, p, i64, p, i32, p, p, p, p]
+        L.mccref_consensus_rule.argtypes = [p, p, i64, p, i32, p, p, p, p, i32]
         L.mccref_canonicalize.argtypes = [p, p, i64, p]
         L.mccref_compare.argtypes = [p, p, i64, p]
         L.mccref_split_join_matrix.argtypes = [p, i32, i64, p]
         L.mccref_group.argtypes = [p, i32, i64, p, p]
         L.mccref_elbow_lambda.argtypes = [p, i32, p]
         for f in ("mccref_mirkin", "mccref_objective", "mccref_delta", "mccref_score",
-                  "mccref_consensus", "mccref_canonicalize", "mccref_compare",
+                  "mccref_consensus", "mccref_consensus_rule", "mccref_canonicalize",
+                  "mccref_compare",
                   "mccref_split_join_matrix", "mccref_group", "mccref_elbow_lambda"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
@@ -152,6 +154,34 @@ def consensus(row_ptr, col, labels, init=None, max_rounds=0, literal=False, trac
     rc = lib().mccref_consensus(_ptr(row_ptr), _ptr(col), n, _ptr(labels), labels.shape[0],
                                 _ptr(ini), out.ctypes.data, ctypes.byref(st),
                                 tr.ctypes.data if tr is not None else None)
+    _check(rc)
+    d = st.as_dict()
+    if tr is not None:
+        tr = tr[: d["passes"]]
+    return out[:n], d, tr
+
+
+RULES = {"pinned": 0, "one_best": 1, "alternate": 2, "unchecked": 3}
+
+
+def consensus_rule(row_ptr, col, labels, init=None, rule="pinned", max_rounds=0, literal=False,
+                   trace=False):
+    """The consensus under one of the round rules of ``RULES`` (Methods,
+    "Parallel algorithm"): the pinned rule, one best move per pass, direction
+    alternation, or the unchecked batch.  Returns ``(out, stats, trace)``."""
+    row_ptr = np.ascontiguousarray(row_ptr, np.int64)
+    col, labels = _i32(col), _i32(labels)
+    n = row_ptr.size - 1
+    ini = None if init is None else _i32(init)
+    out = np.zeros(max(n, 1), np.int32)
+    st = Stats()
+    st.max_rounds = max_rounds
+    st.literal_self_term = int(literal)
+    mr = max_rounds if max_rounds > 0 else 1000
+    tr = np.zeros((mr, 4), np.int64) if trace else None
+    rc = lib().mccref_consensus_rule(_ptr(row_ptr), _ptr(col), n, _ptr(labels), labels.shape[0],
+                                     _ptr(ini), out.ctypes.data, ctypes.byref(st),
+                                     tr.ctypes.data if tr is not None else None, RULES[rule])
     _check(rc)
     d = st.as_dict()
     if tr is not None:

@@ -195,15 +195,18 @@ int mccref_delta(const int32_t* c, const int32_t* labels, int32_t k, int64_t n, 
 /* ------------------------------------------------------------------------ */
 /* Candidates are the clusters holding a graph neighbour of v, other than
  * v's own; self-loops are ignored and repeated clusters counted once.  The
- * argmin is over (gain, cluster id), so ties go to the smallest id. */
+ * argmin is over (gain, cluster id), so ties go to the smallest id.
+ * dir > 0 keeps only candidates with ids above C(v), dir < 0 only those
+ * below (the direction-alternation ablation); dir = 0 keeps all. */
 static void score_vertex(const int64_t* row_ptr, const int32_t* col, const int32_t* labels,
-                         const int32_t* c, const counts* t, int64_t v, int literal,
+                         const int32_t* c, const counts* t, int64_t v, int literal, int dir,
                          int32_t* scratch, int32_t* best, int64_t* dbest, int32_t* ncand) {
   int32_t cv = c[v];
   int64_t m = 0;
   for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
     int32_t u = col[j];
     if (u == v || c[u] == cv) continue;
+    if ((dir > 0 && c[u] < cv) || (dir < 0 && c[u] > cv)) continue;
     scratch[m++] = c[u];
   }
   qsort(scratch, (size_t)m, sizeof(int32_t), cmp_i32);
@@ -261,7 +264,7 @@ int mccref_score(const int64_t* row_ptr, const int32_t* col, int64_t n, const in
   }
   counts_build(&t, c, labels);
   for (int64_t v = v_begin; v < v_end; ++v)
-    score_vertex(row_ptr, col, labels, c, &t, v, literal_self_term, scratch,
+    score_vertex(row_ptr, col, labels, c, &t, v, literal_self_term, 0, scratch,
                  best + (v - v_begin), dbest + (v - v_begin), ncand + (v - v_begin));
   free(t.pairs);
   free(t.size);
@@ -337,7 +340,7 @@ int mccref_consensus(const int64_t* row_ptr, const int32_t* col, int64_t n,
      * at the start of the pass (Methods, "Parallel algorithm"). */
     counts_build(&t, C, labels);
     for (int64_t v = 0; v < n; ++v)
-      score_vertex(row_ptr, col, labels, C, &t, v, literal, scratch, &best[v], &dbest[v],
+      score_vertex(row_ptr, col, labels, C, &t, v, literal, 0, scratch, &best[v], &dbest[v],
                    &ncand[v]);
     st.passes += 1;
     int64_t accepted = 0;
@@ -415,6 +418,119 @@ int mccref_consensus(const int64_t* row_ptr, const int32_t* col, int64_t n,
 done:
   free(t.pairs); free(t.size); free(C); free(CA); free(best); free(dbest); free(ncand);
   free(own_d); free(own_w); free(buf); free(scratch);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Round-rule ablations                                                       */
+/* ------------------------------------------------------------------------ */
+int mccref_consensus_rule(const int64_t* row_ptr, const int32_t* col, int64_t n,
+                          const int32_t* labels, int32_t k, const int32_t* init,
+                          int32_t* out, mccref_stats* stats, int64_t* trace, int32_t rule) {
+  if (rule == MCCREF_RULE_PINNED)
+    return mccref_consensus(row_ptr, col, n, labels, k, init, out, stats, trace);
+  if (rule != MCCREF_RULE_ONE_BEST && rule != MCCREF_RULE_ALTERNATE &&
+      rule != MCCREF_RULE_UNCHECKED)
+    return MCCREF_EINVAL;
+  int rc = common_args_ok(row_ptr, col, n, labels, k);
+  if (rc) return rc;
+  if (n > 0 && !out) return MCCREF_EINVAL;
+  if (init)
+    for (int64_t v = 0; v < n; ++v)
+      if (init[v] < 0 || init[v] >= n) return MCCREF_EINVAL;
+  int32_t max_rounds = (stats && stats->max_rounds > 0) ? stats->max_rounds : 1000;
+  int literal = stats ? stats->literal_self_term : 0;
+  mccref_stats st;
+  memset(&st, 0, sizeof st);
+  st.max_rounds = max_rounds;
+  st.literal_self_term = literal;
+  if (n == 0) {
+    st.passes = 1;
+    st.converged = 1;
+    if (stats) *stats = st;
+    return 0;
+  }
+
+  counts t = {k, n, NULL, NULL};
+  t.pairs = (int64_t*)malloc((size_t)k * (size_t)n * sizeof(int64_t));
+  t.size = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int32_t* C = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  int32_t* best = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  int64_t* dbest = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int32_t* ncand = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+  int64_t* buf = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+  int32_t* scratch = (int32_t*)malloc((size_t)(max_degree(row_ptr, n) + 1) * sizeof(int32_t));
+  if (!t.pairs || !t.size || !C || !best || !dbest || !ncand || !buf || !scratch) {
+    rc = MCCREF_ENOMEM;
+    goto done;
+  }
+
+  for (int64_t v = 0; v < n; ++v) C[v] = init ? init[v] : (int32_t)v;
+  int64_t O = objective_plain(C, labels, k, n, buf);
+  st.objective_init = O;
+  int32_t empty_run = 0; /* consecutive passes without an accepted move */
+
+  for (;;) {
+    /* direction of this pass under ALTERNATE: up on even passes */
+    int dir = rule == MCCREF_RULE_ALTERNATE ? (st.passes % 2 == 0 ? 1 : -1) : 0;
+    counts_build(&t, C, labels);
+    for (int64_t v = 0; v < n; ++v)
+      score_vertex(row_ptr, col, labels, C, &t, v, literal, dir, scratch, &best[v], &dbest[v],
+                   &ncand[v]);
+    st.passes += 1;
+    int64_t accepted = 0, pick = -1;
+    for (int64_t v = 0; v < n; ++v) {
+      st.candidate_evals += ncand[v];
+      if (!(ncand[v] > 0 && dbest[v] < 0)) continue;
+      ++accepted;
+      if (pick < 0 || pair_less(dbest[v], v, dbest[pick], pick)) pick = v;
+    }
+    int64_t committed = 0;
+    if (accepted > 0) {
+      if (rule == MCCREF_RULE_ONE_BEST) {
+        C[pick] = best[pick];
+        committed = 1;
+      } else {
+        /* every accepted move at once, from the frozen state: best[] was
+         * computed before any C changes */
+        for (int64_t v = 0; v < n; ++v)
+          if (ncand[v] > 0 && dbest[v] < 0) C[v] = best[v];
+        committed = accepted;
+      }
+      O = objective_plain(C, labels, k, n, buf);
+      empty_run = 0;
+    } else {
+      empty_run += 1;
+    }
+    st.moves += committed;
+    if (trace) {
+      int64_t* r = trace + (int64_t)(st.passes - 1) * 4;
+      r[0] = accepted;
+      r[1] = committed;
+      r[2] = 0;
+      r[3] = O;
+    }
+    /* no improving move left: one empty pass, or under ALTERNATE one empty
+     * pass in each direction */
+    if (empty_run >= (rule == MCCREF_RULE_ALTERNATE ? 2 : 1)) {
+      st.converged = 1;
+      break;
+    }
+    if (st.passes >= max_rounds) {
+      st.converged = 0;
+      break;
+    }
+  }
+
+  memcpy(out, C, (size_t)n * sizeof(int32_t));
+  st.objective = O;
+  st.clusters = distinct_count(C, n, best);
+  if (stats) *stats = st;
+  rc = 0;
+
+done:
+  free(t.pairs); free(t.size); free(C); free(best); free(dbest); free(ncand); free(buf);
+  free(scratch);
   return rc;
 }
 

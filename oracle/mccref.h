@@ -84,6 +84,36 @@ int mccref_consensus(const int64_t* row_ptr, const int32_t* col, int64_t n,
                      const int32_t* labels, int32_t k, const int32_t* init,
                      int32_t* out, mccref_stats* stats, int64_t* trace);
 
+/* ---- round-rule ablations (Methods, "Parallel algorithm") -------------- */
+/* The paper applies every vertex's best move together and notes that the
+ * sequential alternative, one best move per iteration, converges to the same
+ * quality in fewer moves per iteration; it leaves its validation checks
+ * unspecified.  These rules run on the same scoring as mccref_consensus:
+ *
+ *   MCCREF_RULE_PINNED     the rule of mccref_consensus (batch, validated,
+ *                          conflict-free fallback).
+ *   MCCREF_RULE_ONE_BEST   every pass scores all vertices, then applies only
+ *                          the smallest (gain, vertex) accepted move.
+ *   MCCREF_RULE_ALTERNATE  even passes allow moves only to larger cluster ids,
+ *                          odd passes only to smaller ones; the batch is
+ *                          applied unchecked; the solve stops after two
+ *                          consecutive passes without a move (one in each
+ *                          direction), i.e. when no improving move is left.
+ *   MCCREF_RULE_UNCHECKED  the batch is applied unchecked (may oscillate;
+ *                          converged = 0 at the pass cap).
+ *
+ * Arguments, stats and trace as for mccref_consensus; the trace's third
+ * column is the fallback flag under the pinned rule, 0 otherwise.
+ * candidate_evals counts the candidates scored (under ALTERNATE, those in
+ * the pass's direction). */
+#define MCCREF_RULE_PINNED 0
+#define MCCREF_RULE_ONE_BEST 1
+#define MCCREF_RULE_ALTERNATE 2
+#define MCCREF_RULE_UNCHECKED 3
+int mccref_consensus_rule(const int64_t* row_ptr, const int32_t* col, int64_t n,
+                          const int32_t* labels, int32_t k, const int32_t* init,
+                          int32_t* out, mccref_stats* stats, int64_t* trace, int32_t rule);
+
 /* Relabel cluster ids in [0, n) to [0, clusters) in order of first occurrence. */
 int mccref_canonicalize(const int32_t* in, int32_t* out, int64_t n, int32_t* clusters);
 
