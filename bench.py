@@ -207,6 +207,17 @@ def score_bytes(inst, passes, boundary, accepted):
     return passes * per_pass + 4 * k * boundary + 8 * accepted
 
 
+def scorer_source_sha():
+    """sha256 of the scoring kernels' source: the shared header and pass.hip
+    through the end of k_score_tile (the control and apply kernels follow)."""
+    csrc = os.path.join(ROOT, "paper_2408_11331_amd", "csrc")
+    hdr = open(os.path.join(csrc, "impl.h"), "rb").read()
+    src = open(os.path.join(csrc, "pass.hip"), "rb").read()
+    i = src.index(b"void k_score_tile(")
+    j = src.index(b"\n}\n", i) + 3
+    return hashlib.sha256(hdr + src[:j]).hexdigest()
+
+
 def traffic_from_profile(kernel_src_sha):
     """HBM bytes per scoring launch measured by rocprofv3 counters, if the
     committed measurement was taken on the current kernel source."""
@@ -339,9 +350,8 @@ def main():
     score_ms = sum(st["ms_score"] for st in stats) / args.steps
     bytes_solve = score_bytes(inst, passes, st_ref["boundary"], accepted)
     achieved = bytes_solve / (score_ms / 1000.0) / 1e9
-    src = open(os.path.join(ROOT, "paper_2408_11331_amd", "csrc", "pass.hip"), "rb").read()
     # the counters were taken on this workload from the first input partition
-    traffic = traffic_from_profile(hashlib.sha256(src).hexdigest()) if args.init == "p0" else None
+    traffic = traffic_from_profile(scorer_source_sha()) if args.init == "p0" else None
 
     rec = {
         "metric": METRIC,
