@@ -109,3 +109,30 @@ def test_group_from_distances_rejects_bad_matrix():
         mcc.group_from_distances(np.array([[0, 1], [2, 0]]), 3)
     with pytest.raises(mcc.MccError):
         mcc.group_from_distances(np.array([[0, -1], [-1, 0]]), 3)
+
+
+def test_bench_refuses_several_gpus():
+    # the bench measures one GPU; asking for more exits with a message and
+    # status 2 before touching a device
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "4"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout
+
+
+def test_bench_traffic_keyed_to_scorer_source():
+    # the committed HBM counters apply while the scoring kernels' source is
+    # the one they were taken on
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(b)
+    sha = b.scorer_source_sha()
+    assert len(sha) == 64
+    assert b.traffic_from_profile("0" * 64) is None
+    t = b.traffic_from_profile(sha)
+    assert t is None or t > 0
