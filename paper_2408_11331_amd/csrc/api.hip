@@ -1,4 +1,4 @@
-// Host side of libmcc: argument checks, stream-ordered workspace, the setup
+// Host side of libmcc: argument checks, the workspace cache, the setup
 // sequence and the device-driven pass loop behind the C interface in
 // include/mcc.h.
 #include <stdio.h>
@@ -51,8 +51,6 @@ struct Status {
   int code;
 };
 
-// Stream-ordered scratch allocations, released on the same stream when the
-// call returns (the pool keeps them warm for the next call).
 // Workspace chunks kept between calls, per (device, stream): a call takes the
 // chunks its stream left and gives them back when it returns, so steady-state
 // calls allocate and free nothing (allocation and free calls cost about a
