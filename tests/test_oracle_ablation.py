@@ -198,3 +198,17 @@ def test_converged_rules_leave_no_improving_move(rule, seed):
     assert st["converged"] == 1
     best, dbest, ncand = oracle.score(inst.row_ptr, inst.col, inst.labels, out)
     assert not np.any((ncand > 0) & (dbest < 0))
+
+
+def test_ablation_study_script_runs():
+    # the study script on one small instance: a row per rule and init, and
+    # the summary table
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-m", "oracle.ablation", "--count", "1", "--n-max", "120"],
+                       cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    rows = [l for l in r.stdout.splitlines() if l.startswith("| 0 |")]
+    assert len(rows) == 2 * 5
+    assert "| P_0 | one_best |" in r.stdout and "| singletons | pinned |" in r.stdout
