@@ -197,14 +197,51 @@ def bench_served(args):
     }
 
 
-def score_bytes(inst, passes, boundary, accepted):
-    """Algorithmic HBM bytes of all scoring launches of one solve: per pass
-    the CSR (row_ptr, col), the consensus array and the proposal array once,
-    plus the label row of every vertex that had a candidate and the gain of
-    every proposer."""
+def pass_bytes(inst):
+    """Algorithmic HBM bytes of one local-move pass: the label row of every
+    vertex (4 n k), the row offsets (8 (n + 1)), the arcs (4 nnz), the
+    consensus read (4 n) and the proposal written (4 n)."""
+    n, nnz, k = inst.n, inst.nnz, inst.k
+    return 4 * n * k + 8 * (n + 1) + 4 * nnz + 4 * n + 4 * n
+
+
+def boundary_bytes(inst, passes, boundary, accepted):
+    """The same, counting label rows only for the vertices that had a
+    candidate (the rows a pass actually reads) plus the gain of every
+    proposer, summed over the passes of one solve."""
     n, nnz, k = inst.n, inst.nnz, inst.k
     per_pass = 8 * (n + 1) + 4 * nnz + 4 * n + 4 * n
     return passes * per_pass + 4 * k * boundary + 8 * accepted
+
+
+def host_cpu():
+    """The host's processor model and the cores this process may use."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def golden_record(inst, init_kind):
+    """The stored oracle result for this instance and start, if one exists
+    for exactly this instance (same digest)."""
+    p = os.path.join(ROOT, "tests", "golden", f"{inst.name}.json")
+    if not os.path.exists(p):
+        return None
+    digest = inst.digest()
+    for rec in json.load(open(p)).get("solves", []):
+        if rec["digest"] == digest and rec["init"] == init_kind:
+            return rec
+    return None
 
 
 def scorer_source_sha():
@@ -250,7 +287,7 @@ def cpu_baseline(inst, sample):
     scale = inst.n / sample
     rate = evals * scale / (t_build + t_score * scale)
     return {
-        "value": rate, "unit": "evals/s", "cores": 1, "kind": "oracle",
+        "value": rate, "unit": "evals/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
         "sample": (f"pass 0 of the same instance: counts rebuilt over all {inst.n} vertices "
                    f"({t_build:.1f} s) and the first {sample} vertices scored ({t_score:.1f} s, "
                    f"{evals} candidate evals); rate extrapolated to the whole pass"),
@@ -348,10 +385,21 @@ def main():
     ms_per_step = 1000.0 * elapsed / args.steps
     passes = st_ref["passes"]
     score_ms = sum(st["ms_score"] for st in stats) / args.steps
-    bytes_solve = score_bytes(inst, passes, st_ref["boundary"], accepted)
-    achieved = bytes_solve / (score_ms / 1000.0) / 1e9
+    launch_ms = score_ms / passes
+    per_launch = pass_bytes(inst)
+    achieved = per_launch / (launch_ms / 1000.0) / 1e9
+    per_launch_b = boundary_bytes(inst, passes, st_ref["boundary"], accepted) / passes
     # the counters were taken on this workload from the first input partition
     traffic = traffic_from_profile(scorer_source_sha()) if args.init == "p0" else None
+    # the solve against the oracle's stored result for this very instance
+    gold = golden_record(inst, args.init)
+    if gold is not None:
+        got = hashlib.sha256(out.cpu().numpy().astype("<i4").tobytes()).hexdigest()
+        assert got == gold["out_sha256"], "output differs from the oracle's"
+        for key, val in gold["stats"].items():
+            assert st_ref[key] == val, f"{key}: {st_ref[key]} != oracle {val}"
+        assert [list(r) for r in trace] == gold["trace"], "per-pass trace differs"
+        log("solve equals the oracle's stored result (labels, statistics, trace)")
 
     rec = {
         "metric": METRIC,
@@ -380,16 +428,24 @@ def main():
             "score_kernel_ms_per_solve": score_ms,
         },
         "roofline": {
-            "kernel": "k_score",
+            "kernel": "k_score_tile (with the deferred-vertex k_score of the same pass)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None if traffic is None else traffic,
-            "algorithmic_bytes_per_launch": bytes_solve / passes,
-            "avg_launch_ms": score_ms / passes,
+            "bytes_formula": "4nk + 8(n+1) + 4nnz + 8n per launch",
+            "algorithmic_bytes_per_launch": per_launch,
+            "avg_launch_ms": launch_ms,
+            "boundary_rows_only": {
+                "bytes_per_launch": per_launch_b,
+                "achieved": per_launch_b / (launch_ms / 1000.0) / 1e9,
+                "frac": per_launch_b / (launch_ms / 1000.0) / 1e9 / HBM_PEAK_GBS,
+            },
         },
+        "oracle_checked": gold is not None,
+        "instance_digest": inst.digest(),
     }
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, inst.n)

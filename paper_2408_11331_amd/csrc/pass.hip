@@ -750,8 +750,16 @@ constexpr int kHashSlots = 4096;
 constexpr int kHashOpen = kHashSlots / 2;  // keys the table takes
 constexpr int kHashProbe = 32;
 
-__device__ inline void agg_add(int32_t* hkey, int32_t* hval, int32_t* fill, const PassArgs& a,
-                               int64_t key, int32_t d, int64_t* dn2, int64_t* ds2) {
+// The changes of the sums of squares caused by one global update: the
+// contingency part (n) and the size part (s).  Returned by value: pointers
+// to the caller's accumulators would keep them in scratch memory.
+struct Sq2 {
+  int64_t n, s;
+};
+
+__device__ __attribute__((always_inline)) inline Sq2 agg_add(int32_t* hkey, int32_t* hval,
+                                                           int32_t* fill, const PassArgs& a,
+                                                           int64_t key, int32_t d) {
   const int32_t k32 = (int32_t)key;
   uint32_t h = ((uint32_t)k32 * 2654435761u) >> 20;  // 12 bits: kHashSlots
 #pragma unroll 1
@@ -767,17 +775,16 @@ __device__ inline void agg_add(int32_t* hkey, int32_t* hval, int32_t* fill, cons
     }
     if (cur == k32) {
       atomicAdd(&hval[h], d);
-      return;
+      return Sq2{0, 0};
     }
     h = (h + 1) & (kHashSlots - 1);
   }
   if (key < a.cells) {
     const int32_t old = atomicAdd(counter(a.t, (uint32_t)key), d);
-    *dn2 += 2 * (int64_t)old * d + 1;
-  } else {
-    const int32_t old = atomicAdd(&a.s[key - a.cells], d);
-    *ds2 += 2 * (int64_t)old * d + 1;
+    return Sq2{2 * (int64_t)old * d + 1, 0};
   }
+  const int32_t old = atomicAdd(&a.s[key - a.cells], d);
+  return Sq2{0, 2 * (int64_t)old * d + 1};
 }
 
 __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
@@ -817,12 +824,14 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
       const int32_t* row = a.Lvm + w * a.k;
       for (int i = gl; i < a.k; i += kApplyLanes) {
         const int32_t l = row[i];
-        agg_add(hkey, hval, &fill, a, cell_upd(a.t, i, to, l, claimed), +1, &dn2, &ds2);
-        agg_add(hkey, hval, &fill, a, cell_upd(a.t, i, from, l, claimed), -1, &dn2, &ds2);
+        const Sq2 u = agg_add(hkey, hval, &fill, a, cell_upd(a.t, i, to, l, claimed), +1);
+        const Sq2 w = agg_add(hkey, hval, &fill, a, cell_upd(a.t, i, from, l, claimed), -1);
+        dn2 += u.n + w.n;
       }
       if (gl == 0) {
-        agg_add(hkey, hval, &fill, a, a.cells + to, +1, &dn2, &ds2);
-        agg_add(hkey, hval, &fill, a, a.cells + from, -1, &dn2, &ds2);
+        const Sq2 u = agg_add(hkey, hval, &fill, a, a.cells + to, +1);
+        const Sq2 w = agg_add(hkey, hval, &fill, a, a.cells + from, -1);
+        ds2 += u.s + w.s;
       }
     }
   }

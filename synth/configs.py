@@ -214,3 +214,32 @@ def random_instance(n, k, avg_deg, n_labels, seed, init="p0", self_loops=0, dup_
         ini = rng.integers(0, n, size=n).astype(np.int32)
     return Instance("random", row_ptr, col, np.ascontiguousarray(labels), ini.astype(np.int32),
                     labels[0].copy(), dict(n=n, k=k, seed=seed))
+
+
+SERVED_LARGE = (200_000, 500_000, 1_000_000)
+
+
+def served_pool_specs(small=16, large=SERVED_LARGE):
+    """The request pool of the served workload: ``small`` LFR-style graphs
+    with n log-uniform in [1000, 50000] and k uniform in [4, 16], and large
+    ones (the given sizes, mean degree 16, k = 32).  Arrivals draw small
+    requests four times as often as large ones in total (80/20)."""
+    rng = np.random.Generator(np.random.PCG64(MASTER + 4))
+    specs = []
+    for j in range(small):
+        n = int(np.exp(rng.uniform(np.log(1000), np.log(50_000))))
+        specs.append(dict(index=j, n=n, k=int(rng.integers(4, 17)), large=False))
+    for j, n in enumerate(large):
+        specs.append(dict(index=small + j, n=int(n), k=32, large=True))
+    return specs
+
+
+def served_instance(spec):
+    """One request of the served pool (seeded by its index)."""
+    n = spec["n"]
+    inst = lfr(n=n, k=spec["k"], w=4 + 1000 + spec["index"],
+               mean_deg=16.0 if spec["large"] else 20.0, max_deg=200, min_comm=50,
+               max_comm=1000)
+    inst.name = "served"
+    inst.meta.update(spec)
+    return inst

@@ -7,6 +7,9 @@ method; these are the inputs both the oracle and the GPU library consume.
 """
 from __future__ import annotations
 
+import os
+import subprocess
+
 import numpy as np
 
 
@@ -239,11 +242,16 @@ def zipf_sizes(n: int, ncomp: int, a: float) -> np.ndarray:
     return sizes
 
 
-def gmm_points(n: int, dim: int, ncomp: int, zipf_a: float, sigma_m: float, rng):
-    """Points from a Gaussian mixture with unit covariance, in random order.
+def gmm_points(n: int, dim: int, ncomp: int, zipf_a: float, sigma_m: float, rng,
+               scale: int = 32, clip: int = 300):
+    """Points from a Gaussian mixture with unit covariance, in random order,
+    on an integer grid.
 
     Component means are N(0, sigma_m^2 I); component sizes follow Zipf(a).
-    Returns ``(points float32[n, dim], truth int32[n])``.
+    Coordinates are rounded to multiples of 1/scale and stored as integers
+    (x * scale, clipped to [-clip, clip]), so that every distance between
+    points is an exact integer and the kNN graph is the same on any device.
+    Returns ``(points int32[n, dim], truth int32[n])``.
     """
     sizes = zipf_sizes(n, ncomp, zipf_a)
     means = rng.normal(0.0, sigma_m, size=(ncomp, dim))
@@ -252,31 +260,107 @@ def gmm_points(n: int, dim: int, ncomp: int, zipf_a: float, sigma_m: float, rng)
     truth = truth[perm]
     pts = rng.standard_normal(size=(n, dim), dtype=np.float32)
     pts += means[truth].astype(np.float32)
-    return pts, truth
+    q = np.clip(np.rint(pts * np.float32(scale)), -clip, clip).astype(np.int32)
+    return q, truth
 
 
-def knn_graph(points: np.ndarray, kk: int, device: str = "cpu", chunk: int = 0):
-    """Exact symmetrised (union) kNN graph under L2 distance.
+_KNN_C = os.path.join(os.path.dirname(os.path.abspath(__file__)), "knn.c")
+_KNN_SO = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libknn.so")
 
-    Uses torch for the distance blocks and top-k (on ``device``).  Returns
-    ``(row_ptr, col)``.
-    """
+
+def build_knn(force: bool = False) -> str:
+    """Compile the exact CPU kNN search (knn.c) next to its source."""
+    if force or not os.path.exists(_KNN_SO) or \
+            os.path.getmtime(_KNN_SO) < os.path.getmtime(_KNN_C):
+        tmp = _KNN_SO + ".tmp"
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared",
+                               _KNN_C, "-o", tmp, "-lm"])
+        os.replace(tmp, _KNN_SO)
+    return _KNN_SO
+
+
+def _exact_range_ok(points: np.ndarray) -> bool:
+    m = int(np.abs(points).max()) if points.size else 0
+    return 4 * points.shape[1] * m * m < (1 << 24)
+
+
+def knn_lists_cpu(points: np.ndarray, kk: int) -> np.ndarray:
+    """Exact kNN lists (squared L2, ties to the lower index) by the
+    compiled CPU search; int32[n, kk]."""
+    import ctypes
+    pts = np.ascontiguousarray(points, np.int32)
+    n, dim = pts.shape
+    out = np.empty((n, kk), np.int32)
+    L = ctypes.CDLL(build_knn())
+    L.knn_exact.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                            ctypes.c_void_p]
+    L.knn_exact.restype = ctypes.c_int
+    rc = L.knn_exact(pts.ctypes.data, n, dim, kk, out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"knn_exact failed ({rc})")
+    return out
+
+
+def knn_lists_torch(points: np.ndarray, kk: int, device: str = "cpu", chunk: int = 0,
+                    extra: int = 9) -> np.ndarray:
+    """Exact kNN lists with torch (CPU or GPU); int32[n, kk].
+
+    Distances of integer points are exact integers below 2^24, computed
+    exactly in single precision (checked on one full row per block against
+    integer arithmetic).  Each row keeps its ``kk + extra`` smallest
+    distances, re-ranked by (distance, index); a row whose (kk + extra)-th
+    distance still equals its kk-th (a tie that may reach past the kept
+    entries) is recomputed over all points by (distance, index) keys."""
     import torch
 
-    n = points.shape[0]
-    X = torch.from_numpy(np.ascontiguousarray(points)).to(device)
+    n, dim = points.shape
+    Xl = torch.from_numpy(np.ascontiguousarray(points, np.int64)).to(device)
+    X = Xl.float()
     sq = (X * X).sum(dim=1)
     if chunk <= 0:
-        # bound the distance block at ~2 GiB of fp32
-        chunk = max(1, min(n, (1 << 29) // max(n, 1)))
+        chunk = max(1, min(n, (1 << 28) // max(n, 1)))
+    m = min(kk + extra, n - 1)
+    ar = torch.arange(n, device=device, dtype=torch.int64)
     nbr = torch.empty((n, kk), dtype=torch.int64, device=device)
     for s in range(0, n, chunk):
         e = min(n, s + chunk)
-        q = X[s:e]
-        d = sq[s:e, None] - 2.0 * (q @ X.T) + sq[None, :]
-        idx = torch.arange(s, e, device=device)
-        d[idx - s, idx] = float("inf")
-        nbr[s:e] = torch.topk(d, kk, dim=1, largest=False, sorted=False).indices
-    nb = nbr.cpu().numpy()
+        d = X[s:e] @ X.T
+        d.mul_(-2.0).add_(sq[None, :]).add_(sq[s:e, None])
+        # the block is exact: one row against integer arithmetic
+        ref = ((Xl[s][None, :] - Xl) ** 2).sum(dim=1)
+        if not torch.equal(d[0].long(), ref):
+            raise RuntimeError("distance block is not exact on this device")
+        rows = torch.arange(s, e, device=device)
+        d[rows - s, rows] = float("inf")
+        val, idx = torch.topk(d, m, dim=1, largest=False, sorted=True)
+        key = (val.long() << 32) | idx
+        key, _ = torch.sort(key, dim=1)
+        nbr[s:e] = key[:, :kk] & 0xffffffff
+        tied = torch.nonzero(val[:, m - 1] == val[:, kk - 1]).flatten()
+        for r in tied.tolist():
+            full = (d[r].long() << 32) | ar
+            full[s + r] = torch.iinfo(torch.int64).max
+            nbr[s + r] = torch.topk(full, kk, largest=False, sorted=True).values & 0xffffffff
+        del d
+    return nbr.to(torch.int32).cpu().numpy()
+
+
+def knn_graph(points: np.ndarray, kk: int, device: str = "cpu", chunk: int = 0):
+    """Exact symmetrised (union) kNN graph of integer points under the
+    squared L2 distance, ties to the lower index.
+
+    On the CPU the compiled search (knn.c) is used when gcc can build it,
+    else torch; on a GPU, torch.  All give the same lists.  Returns
+    ``(row_ptr, col)``."""
+    if not _exact_range_ok(points):
+        raise ValueError("point coordinates too large for exact distances")
+    n = points.shape[0]
+    if device == "cpu":
+        try:
+            nb = knn_lists_cpu(points, kk)
+        except (OSError, subprocess.CalledProcessError):
+            nb = knn_lists_torch(points, kk, device="cpu", chunk=chunk)
+    else:
+        nb = knn_lists_torch(points, kk, device=device, chunk=chunk)
     u = np.repeat(np.arange(n, dtype=np.int64), kk)
     return csr_from_edges(n, u, nb.reshape(-1))

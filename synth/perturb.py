@@ -141,16 +141,18 @@ def split_bfs(labels: np.ndarray, row_ptr, col, rng, min_factor=2.0, prob=0.25,
 def split_voronoi(labels: np.ndarray, points: np.ndarray, rng, min_factor=2.0,
                   prob=0.25, parts=(2, 3, 4)) -> np.ndarray:
     """Resolution change for point data: split each chosen community by the
-    nearest of 2-4 random member points (feature-space Voronoi cells)."""
+    nearest of 2-4 random member points (feature-space Voronoi cells).
+    ``points`` are integers; distances are exact (int64) and ties go to the
+    first seed."""
     plan = _split_plan(labels, rng, min_factor, prob, parts)
     out = labels.astype(np.int64).copy()
     next_label = int(labels.max()) + 1
     for c, p in plan:
         members = np.nonzero(labels == c)[0]
         seeds = rng.choice(members, size=min(p, members.size), replace=False)
-        X = points[members].astype(np.float32)
-        S = points[seeds].astype(np.float32)
-        d = (X * X).sum(1)[:, None] - 2.0 * X @ S.T + (S * S).sum(1)[None, :]
+        X = points[members].astype(np.int64)
+        S = points[seeds].astype(np.int64)
+        d = (X * X).sum(1)[:, None] - 2 * (X @ S.T) + (S * S).sum(1)[None, :]
         near = np.argmin(d, axis=1)
         newl = np.array([c] + list(range(next_label, next_label + len(seeds) - 1)))
         next_label += len(seeds) - 1

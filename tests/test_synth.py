@@ -47,3 +47,25 @@ def test_generators_are_deterministic():
     c = synth.gmm_knn(n=3000, k=3)
     d = synth.gmm_knn(n=3000, k=3)
     assert np.array_equal(c.col, d.col) and np.array_equal(c.labels, d.labels)
+
+
+def test_knn_exact_on_every_path():
+    """The kNN lists of integer points are exact (squared L2, ties to the
+    lower index) on the compiled CPU search and on the torch path alike, so
+    the 2M-point workload is the same instance on any machine.  Checked
+    against brute force, including points placed to tie."""
+    from synth import graph as G
+    rng = np.random.Generator(np.random.PCG64(7))
+    pts, _ = G.gmm_points(2500, 30, 20, 1.2, 0.8, rng)
+    # exact duplicates and mirror images make equal distances
+    pts[100:140] = pts[50]
+    pts[200:230] = 2 * pts[7] - pts[300:330]
+    a = G.knn_lists_cpu(pts, 15)
+    b = G.knn_lists_torch(pts, 15, chunk=333)
+    X = pts.astype(np.int64)
+    for q in range(pts.shape[0]):
+        d = ((X - X[q]) ** 2).sum(1)
+        d[q] = np.iinfo(np.int64).max
+        ref = np.lexsort((np.arange(d.size), d))[:15]
+        assert np.array_equal(a[q], ref), q
+    assert np.array_equal(a, b)
