@@ -44,6 +44,11 @@ extern "C" {
 #define MCC_EDEVICE (-4)  /* a HIP runtime call failed; see mcc_strerror */
 #define MCC_ENOTSUP (-5)  /* the instance needs a table larger than the library
                              supports (see mcc_consensus) */
+#define MCC_ESCRATCH (-6) /* mcc_consensus_noalloc: the instance needs more
+                             workspace than the scratch array holds */
+
+/* Size of the per-device scratch array of mcc_consensus_noalloc, MiB. */
+#define MCC_NOALLOC_SCRATCH_MIB 256
 
 /* ---- flags --------------------------------------------------------------- */
 #define MCC_F_VALIDATE 0x1u /* check the CSR on the device before solving */
@@ -159,6 +164,24 @@ typedef struct {
  */
 int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k,
                   const int32_t* init, int32_t* out, mcc_stats* stats);
+
+/*
+ * mcc_consensus for callers that cannot allocate device memory (code being
+ * captured into a HIP graph, tight serving loops, hosts that forbid
+ * hipMalloc): the same arguments, the same results bit for bit, but the
+ * workspace is a static device array of MCC_NOALLOC_SCRATCH_MIB MiB inside
+ * the library (each device the library runs on holds its own copy from the
+ * library's first use there until the process ends) and the call makes no
+ * hipMalloc or hipFree.  Instances whose workspace exceeds the array
+ * (roughly 4 n k + 48 n bytes plus the contingency tables) fail with
+ * MCC_ESCRATCH before anything is computed, or during set-up when the
+ * tables turn out too large; the outputs are then unspecified.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents: calls that overlap on one device (on different streams
+ * or host threads) race and give wrong results; serialise them.
+ */
+int mcc_consensus_noalloc(const mcc_csr* g, const int32_t* const* labels, int32_t k,
+                          const int32_t* init, int32_t* out, mcc_stats* stats);
 
 /*
  * Objective of a given partition: *result (host) = sum_i Mirkin(c, P_i)

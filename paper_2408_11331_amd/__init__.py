@@ -14,11 +14,13 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libmcc.so")
 
 MCC_OK, MCC_EINVAL, MCC_EGRAPH, MCC_ENOMEM, MCC_EDEVICE, MCC_ENOTSUP = 0, -1, -2, -3, -4, -5
+MCC_ESCRATCH = -6
+NOALLOC_SCRATCH_BYTES = 256 << 20
 MCC_F_VALIDATE, MCC_F_TRACE, MCC_F_LITERAL, MCC_F_PROFILE = 0x1, 0x2, 0x4, 0x8
 MCC_F_ARC_CACHE, MCC_F_HASH_TABLES, MCC_F_SYMMETRIC = 0x10, 0x20, 0x40
 
 # every function include/mcc.h declares
-EXPORTS = ("mcc_consensus", "mcc_objective", "mcc_mirkin", "mcc_canonicalize",
+EXPORTS = ("mcc_consensus", "mcc_consensus_noalloc", "mcc_objective", "mcc_mirkin", "mcc_canonicalize",
            "mcc_consensus_batch", "mcc_batch_tune", "mcc_tune_save", "mcc_tune_load",
            "mcc_compare", "mcc_split_join_matrix", "mcc_group_from_distances",
            "mcc_group_partitions", "mcc_release_workspace", "mcc_strerror")
@@ -113,6 +115,9 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         p, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
         L.mcc_consensus.argtypes = [ctypes.POINTER(Csr), p, i32, p, p, ctypes.POINTER(Stats)]
+        L.mcc_consensus_noalloc.argtypes = [ctypes.POINTER(Csr), p, i32, p, p,
+                                            ctypes.POINTER(Stats)]
+        L.mcc_consensus_noalloc.restype = ctypes.c_int
         L.mcc_objective.argtypes = [p, p, i32, i64, p, p]
         L.mcc_mirkin.argtypes = [p, p, i64, p, p]
         L.mcc_canonicalize.argtypes = [p, p, i64, p, p]
@@ -188,13 +193,15 @@ class _Rows:
 
 
 def consensus(row_ptr, col, labels, init=None, *, max_rounds=0, flags=0, lanes=0,
-              stream=None, out=None, trace=False):
+              stream=None, out=None, trace=False, noalloc=False):
     """Greedy median consensus on the GPU.
 
     row_ptr: int64 CUDA tensor [n+1]; col: int32 CUDA tensor [nnz];
     labels: int32 CUDA tensor [k, n] (or k tensors [n]); init: int32 [n] in
-    [0, n) or None (singletons).  Returns ``(out, stats)`` (and the per-pass
-    trace as a list of 4-tuples when ``trace``)."""
+    [0, n) or None (singletons).  ``noalloc`` calls mcc_consensus_noalloc
+    (workspace in the library's static scratch array; pass ``out``).
+    Returns ``(out, stats)`` (and the per-pass trace as a list of 4-tuples
+    when ``trace``)."""
     import torch
     if row_ptr.dtype != torch.int64 or not row_ptr.is_cuda:
         raise TypeError("row_ptr must be a CUDA int64 tensor")
@@ -215,7 +222,8 @@ def consensus(row_ptr, col, labels, init=None, *, max_rounds=0, flags=0, lanes=0
     mr = max_rounds if max_rounds > 0 else 1000
     tbuf = (ctypes.c_int64 * (4 * mr))() if trace else None
     st.trace = ctypes.cast(tbuf, ctypes.c_void_p) if trace else None
-    _check(lib().mcc_consensus(ctypes.byref(g), arr, len(rows),
+    fn = lib().mcc_consensus_noalloc if noalloc else lib().mcc_consensus
+    _check(fn(ctypes.byref(g), arr, len(rows),
                                init.data_ptr() if init is not None else None,
                                out.data_ptr() if n > 0 else None, ctypes.byref(st)))
     d = st.as_dict()

@@ -79,18 +79,20 @@ class Arena {
  public:
   explicit Arena(hipStream_t st) : st_(st) {
     (void)hipGetDevice(&dev_);
-    ChunkCache& c = chunk_cache();
-    std::lock_guard<std::mutex> lock(c.m);
-    auto it = c.free.find({dev_, st_});
-    if (it != c.free.end()) {
-      avail_.swap(it->second);
-      for (const Chunk& k : avail_) c.bytes -= k.size;
-      c.free.erase(it);
-    }
+    take_cached();
+  }
+  // An arena over a fixed device region of `cap` bytes: get() carves from
+  // it and throws Status{MCC_ESCRATCH} when it is full; nothing is
+  // allocated, freed or cached.
+  Arena(hipStream_t st, unsigned char* fixed, size_t cap)
+      : st_(st), fixed_(fixed != nullptr), next_(fixed), left_(fixed ? cap : 0) {
+    (void)hipGetDevice(&dev_);
+    if (!fixed_) take_cached();
   }
   ~Arena() {
     // kernels and queued copies may still use the chunks: drain first
     (void)hipStreamSynchronize(st_);
+    if (fixed_) return;
     ChunkCache& c = chunk_cache();
     std::lock_guard<std::mutex> lock(c.m);
     std::vector<Chunk>& keep = c.free[{dev_, st_}];
@@ -124,6 +126,7 @@ class Arena {
       left_ -= bytes;
       return static_cast<T*>(r);
     }
+    if (fixed_) throw Status{MCC_ESCRATCH};
     const Chunk k = chunk(std::max(bytes, kChunk));
     if (bytes >= kChunk) return static_cast<T*>(k.p);  // own chunk; keep the current one
     next_ = static_cast<unsigned char*>(k.p) + bytes;
@@ -132,6 +135,16 @@ class Arena {
   }
 
  private:
+  void take_cached() {
+    ChunkCache& c = chunk_cache();
+    std::lock_guard<std::mutex> lock(c.m);
+    auto it = c.free.find({dev_, st_});
+    if (it != c.free.end()) {
+      avail_.swap(it->second);
+      for (const Chunk& k : avail_) c.bytes -= k.size;
+      c.free.erase(it);
+    }
+  }
   // The smallest cached chunk of at least `size` bytes, else a new one.
   Chunk chunk(size_t size) {
     size_t best = avail_.size();
@@ -158,12 +171,40 @@ class Arena {
 
   static constexpr size_t kChunk = (size_t)16 << 20;
   hipStream_t st_;
+  bool fixed_ = false;
   int dev_ = 0;
   std::vector<Chunk> used_, avail_;
   unsigned char* next_ = nullptr;
   size_t left_ = 0;
   std::vector<std::vector<unsigned char>> staging_;
 };
+
+// Workspace of mcc_consensus_noalloc: one array per device, held from the
+// library's first use on that device until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it names a
+// stand-in, not device memory): it takes the device address once per device
+// from hipGetSymbolAddress and uses that.
+constexpr size_t kScratchBytes = (size_t)MCC_NOALLOC_SCRATCH_MIB << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_m;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array.
+unsigned char* scratch_address() {
+  int dev = 0;
+  HIPCK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Status{MCC_EDEVICE};
+  std::lock_guard<std::mutex> lock(g_scratch_m);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIPCK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw Status{MCC_EDEVICE};
+    g_scratch_ptr[dev] = static_cast<unsigned char*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
 
 int device_sms() {
   static thread_local int cached = 0;
@@ -521,12 +562,20 @@ const char* mcc_strerror(int code) {
     case MCC_ENOMEM: return "out of device memory";
     case MCC_EDEVICE: return g_hip_error.empty() ? "HIP runtime error" : g_hip_error.c_str();
     case MCC_ENOTSUP: return "instance exceeds the supported table size";
+    case MCC_ESCRATCH:
+      return "instance needs more workspace than the no-allocation scratch array holds";
     default: return "unknown error code";
   }
 }
 
-int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, const int32_t* init,
-                  int32_t* out, mcc_stats* stats) {
+}  // extern "C"
+
+namespace {
+
+// One solve.  noalloc: the workspace is the device's scratch array instead
+// of the cached chunks (nothing is allocated).
+int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
+                   const int32_t* init, int32_t* out, mcc_stats* stats, bool noalloc) {
   if (!g || k < 1 || g->n < 0 || g->nnz < 0) return MCC_EINVAL;
   const int64_t n = g->n;
   const int32_t max_rounds = stats && stats->max_rounds > 0 ? stats->max_rounds : 1000;
@@ -559,8 +608,10 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
     return MCC_EINVAL;
 
   hipStream_t st = stats ? (hipStream_t)stats->stream : nullptr;
+  // the label rows and per-vertex state alone must fit the scratch array
+  if (noalloc && (uint64_t)(4 * n * (int64_t)k + 48 * n) > kScratchBytes) return MCC_ESCRATCH;
   try {
-    Arena ar(st);
+    Arena ar(st, noalloc ? scratch_address() : nullptr, kScratchBytes);
     hipEvent_t e0, e1, e2, e3;
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
@@ -754,6 +805,20 @@ int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, con
   } catch (...) {
     return translate(std::current_exception());
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mcc_consensus(const mcc_csr* g, const int32_t* const* labels, int32_t k, const int32_t* init,
+                  int32_t* out, mcc_stats* stats) {
+  return consensus_impl(g, labels, k, init, out, stats, false);
+}
+
+int mcc_consensus_noalloc(const mcc_csr* g, const int32_t* const* labels, int32_t k,
+                          const int32_t* init, int32_t* out, mcc_stats* stats) {
+  return consensus_impl(g, labels, k, init, out, stats, true);
 }
 
 int mcc_objective(const int32_t* c, const int32_t* const* labels, int32_t k, int64_t n,
