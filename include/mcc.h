@@ -125,6 +125,10 @@ typedef struct {
   int32_t lanes_used;      /* the `lanes` the scoring ran with (0 = tiled) */
   int32_t tables;          /* contingency table layout used: 0 dense blocked,
                               1 dense interleaved, 2 hashed */
+  int64_t skipped_evals;   /* of candidate_evals, those not recomputed because
+                              an exact bound showed the vertex could not
+                              propose (with MCC_F_SYMMETRIC; they count in
+                              candidate_evals as the method scores them) */
 } mcc_stats;
 
 /*

@@ -45,11 +45,12 @@ class Stats(ctypes.Structure):
         ("ms_total", ctypes.c_float), ("ms_passes", ctypes.c_float),
         ("boundary", ctypes.c_int64), ("ms_score", ctypes.c_float),
         ("lanes_used", ctypes.c_int32), ("tables", ctypes.c_int32),
+        ("skipped_evals", ctypes.c_int64),
     ]
 
     OUT = ("passes", "converged", "fallback_rounds", "clusters", "moves", "candidate_evals",
            "objective_init", "objective", "ms_total", "ms_passes", "boundary", "ms_score",
-           "lanes_used", "tables")
+           "lanes_used", "tables", "skipped_evals")
 
     def as_dict(self):
         return {f: getattr(self, f) for f in self.OUT}

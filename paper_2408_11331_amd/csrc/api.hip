@@ -594,6 +594,7 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
     stats->boundary = 0;
     stats->lanes_used = 0;
     stats->tables = 0;
+    stats->skipped_evals = 0;
   }
   if (n == 0) {
     if (stats) {
@@ -662,6 +663,8 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
 
     PassArgs a{};
     a.ctl = ctl;
+    a.pc = ar.get<int64_t>(kPassCounters * kCounterStride);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(a.pc), kPassCounters * kCounterStride, 0ull, st);
     a.n = n;
     a.k = k;
     a.literal = (flags & MCC_F_LITERAL) ? 1 : 0;
@@ -705,7 +708,8 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
       a.Cn = ar.get<uint8_t>(n * a.cn_bytes);
       launch_narrow(S.C, a.Cn, a.cn_bytes, n, st);
     }
-    if (S.total + S.K0 >= ((int64_t)1 << 31)) throw Status{MCC_ENOTSUP};  // 32-bit update keys
+    // 32-bit update keys: cells, cluster sizes, per-cluster move counts
+    if (S.total + 2 * (int64_t)S.K0 >= ((int64_t)1 << 31)) throw Status{MCC_ENOTSUP};
 
     // the tiled scorer packs cluster ids in 24 bits
     const int lanes = (lanes_req == 0 && S.K0 >= (1 << 24)) ? 64 : lanes_req;
@@ -715,6 +719,14 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
       a.ccache = ar.get<int32_t>(n * kCacheCand);
       launch_fill_i32(a.dirty, n, 1, st);
       launch_fill_i32(a.cnum, n, -1, st);
+      a.slack = ar.get<int32_t>(n);
+      a.churn = ar.get<int32_t>(2 * (int64_t)S.K0);
+      a.st = ar.get<int32_t>(n);
+      a.rlist = ar.get<int32_t>(n);
+      a.sparse_max = (int32_t)std::max<int64_t>(1, n / 8);
+      // the cached candidate rows are read as 16-byte vectors
+      launch_fill_i32(a.slack, n, -1, st);
+      launch_fill_i32(a.churn, 2 * (int64_t)S.K0, 0, st);
     }
     const int sms = device_sms();
     const int64_t blocks_needed =
@@ -782,6 +794,7 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
       stats->clusters = clusters;
       stats->moves = hc.moves;
       stats->candidate_evals = hc.evals;
+      stats->skipped_evals = hc.skipped;
       stats->objective_init = (int64_t)k * acc[0] + acc[1] - 2 * acc[2];
       stats->objective = hc.O;
       float ms = 0.f;

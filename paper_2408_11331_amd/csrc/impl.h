@@ -32,7 +32,8 @@ struct Ctl {
   int64_t moves;            // committed moves in all passes
   int64_t boundary;         // vertices with a candidate, summed over passes
   int32_t heavy_count;      // vertices deferred by the tiled scorer this pass
-  int32_t pad2;
+  int32_t rescore_count;    // vertices the status kernel left for scoring
+  int64_t skipped;          // candidate evaluations proven unnecessary (all passes)
   int64_t* trace;           // device int64[max_rounds * 4] or null
 };
 
@@ -293,7 +294,38 @@ struct PassArgs {
   int32_t* dirty;     // n
   int32_t* cnum;      // n: cached candidate count, -1 none
   int32_t* ccache;    // n * kCacheCand
+  // Skipping provably unchanged decisions (with the candidate cache).  The
+  // gain of v for x, 2 (S_c(v) - S_x(v)) + k (|x| - |c| - 1), moves by at
+  // most k for every vertex that enters or leaves c or x (each changes
+  // 2 S_y(v) - k |y| by 2 agree(u, v) - k, between -k and k).  slack[v] is
+  // the smallest gain of v at its last exact scoring (clamped to int32, -1:
+  // none or negative) minus the bounds of the passes since; churn counts the
+  // vertices that entered or left each cluster in the previous pass
+  // (churn[(p & 1) K0 ..] is read by pass p; the other half is filled by
+  // its apply).  A clean vertex whose slack stays >= 0 after subtracting
+  // k (churn of its cluster + largest churn of its cached candidates)
+  // cannot propose, and is not rescored.
+  int32_t* slack;     // n
+  int32_t* churn;     // 2 * K0
+  // Per-pass status (with the candidate cache), written by k_status:
+  // st[v] = -1 when v is settled for this pass (no candidate, or skipped by
+  // the bound; its proposal is already written), 0 when its candidates must
+  // be found from its arcs, c > 0 when its c cached candidates must be
+  // rescored.  rlist holds the vertices with st >= 0 (rescore_count of
+  // them).  Passes with more than sparse_max of them run the tiled scorer
+  // over all tiles, the others the list scorer over rlist.
+  int32_t* st;        // n
+  int32_t* rlist;     // n
+  int32_t sparse_max;
+  int32_t pad3;
+  // Per-pass counters of the scoring kernels (kPassCounters of them, each in
+  // its own 512-byte line so that their atomics do not share an L2 channel),
+  // added once per workgroup and folded into the control block by k_begin.
+  int64_t* pc;        // kPassCounters * kCounterStride
 };
+
+constexpr int kPassCounters = 4;    // evaluations, proposals, boundary vertices, skipped
+constexpr int kCounterStride = 64;  // int64 words between two counters
 
 constexpr int kCacheCand = 8;  // candidate clusters cached per vertex
 

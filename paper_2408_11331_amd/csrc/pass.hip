@@ -70,6 +70,28 @@ __device__ inline int32_t wave_sum32(int32_t x) {
   return x;
 }
 
+// Add the workgroup's totals of the pass counters (all threads call; one
+// atomic per counter and workgroup).
+__device__ inline void flush_counts(const PassArgs& a, int64_t evals, int64_t nprop,
+                                    int64_t boundary, int64_t skipped) {
+  __shared__ int64_t red[kPassCounters][kBlock / 64];
+  const int64_t v[kPassCounters] = {evals, nprop, boundary, skipped};
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < kPassCounters; ++c) {
+    const int64_t x = wave_sum64(v[c]);
+    if (lane == 0) red[c][w] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < kPassCounters) {
+    int64_t tot = 0;
+#pragma unroll
+    for (int j = 0; j < kBlock / 64; ++j) tot += red[threadIdx.x][j];
+    if (tot) atomicAdd((unsigned long long*)&a.pc[threadIdx.x * kCounterStride],
+                       (unsigned long long)tot);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // score: G lanes per vertex.  A lane keeps R neighbour cluster ids and the
 // labels of up to KR partitions in registers; larger degrees or k fall back
@@ -218,6 +240,10 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
           for (int r = 0; r < R; ++r)
             if (x[r] == m) x[r] = kInf;
         }
+        if (a.dirty) {  // the candidate set, cached for later passes
+          if (lane < min(nc, kCacheCand)) a.ccache[v * kCacheCand + lane] = cand_lo;
+          if (lane == 0) a.cnum[v] = nc <= kCacheCand ? nc : -1;
+        }
         if (nc == 0) {
           if (lane == 0) a.prop[v] = kNone;
           continue;
@@ -289,6 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
             a.dprop[v] = bd;
             ++nprop;
           }
+          if (a.slack) a.slack[v] = p ? -1 : (int32_t)min(bd, (int64_t)INT32_MAX);
         }
         continue;
       }
@@ -340,14 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
       }
     }
   }
-  evals = wave_sum64(evals);
-  nprop = wave_sum32(nprop);
-  boundary = wave_sum32(boundary);
-  if ((threadIdx.x & 63) == 0) {
-    if (evals) atomicAdd((unsigned long long*)&a.ctl->pass_evals, (unsigned long long)evals);
-    if (nprop) atomicAdd(&a.ctl->nprop, nprop);
-    if (boundary) atomicAdd((unsigned long long*)&a.ctl->boundary, (unsigned long long)boundary);
-  }
+  flush_counts(a, evals, nprop, boundary, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -399,21 +419,33 @@ void k_score_tile(PassArgs a) {
   int64_t evals = 0;
   int32_t nprop = 0, boundary = 0;
   const int64_t ntiles = (a.n + kBlock - 1) / kBlock;
+  // passes with few vertices to rescore are left to the list scorer
+  if (a.st && a.ctl->rescore_count <= a.sparse_max) return;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t v0 = tile * kBlock;
     const int nv = (int)min((int64_t)kBlock, a.n - v0);
-    const int64_t a0 = a.row_ptr[v0];
-    for (int j = t; j <= nv; j += kBlock) s_off[j] = (int32_t)(a.row_ptr[v0 + j] - a0);
-    s_c[t] = t < nv ? a.C[v0 + t] : -1;
-    int32_t cached = -1;  // candidates of a clean vertex, from the previous pass
-    if (a.dirty && t < nv) {
-      if (!a.dirty[v0 + t]) cached = a.cnum[v0 + t];
-      a.dirty[v0 + t] = 0;  // this pass's moves mark it again
+    const int32_t cv = t < nv ? a.C[v0 + t] : -1;
+    s_c[t] = cv;
+    // candidates of a vertex that need not be found again (from the status
+    // pass: 0 also for a vertex already settled), -1: walk its arcs
+    int32_t cached = -1;
+    if (a.st && t < nv) {
+      const int32_t stv = a.st[v0 + t];
+      cached = stv < 0 ? 0 : (stv > 0 ? stv : -1);
     }
     s_clean[t] = cached >= 0;
     s_nc[t] = cached > 0 ? cached : 0;
     s_def[t] = 0;
     for (int j = t; j < kSetSlots; j += kBlock) s_set[j] = -1;
+    // the arcs are walked only when some vertex of the tile needs them
+    const int walk = __syncthreads_or(t < nv && cached < 0);
+    int64_t a0 = 0;
+    if (walk) {
+      a0 = a.row_ptr[v0];
+      for (int j = t; j <= nv; j += kBlock) s_off[j] = (int32_t)(a.row_ptr[v0 + j] - a0);
+    } else if (t == 0) {
+      s_off[nv] = 0;
+    }
     __syncthreads();
     const int32_t A = s_off[nv];
     // each thread takes U consecutive arcs of every chunk, read as one
@@ -519,6 +551,7 @@ void k_score_tile(PassArgs a) {
       if (def) {
         const int32_t slot = atomicAdd(&a.ctl->heavy_count, 1);
         a.heavy[slot] = (int32_t)v;
+        if (a.slack) a.slack[v] = -1;
       } else if (nc == 0) {
         a.prop[v] = kNone;
       } else {
@@ -681,21 +714,263 @@ void k_score_tile(PassArgs a) {
         a.dprop[v] = bestd;
         ++nprop;
       }
+      if (a.slack) a.slack[v] = p ? -1 : (int32_t)min(bestd, (int64_t)INT32_MAX);
     }
     __syncthreads();
   }
-  evals = wave_sum64(evals);
-  nprop = wave_sum32(nprop);
-  boundary = wave_sum32(boundary);
-  if ((threadIdx.x & 63) == 0) {
-    if (evals) atomicAdd((unsigned long long*)&a.ctl->pass_evals, (unsigned long long)evals);
-    if (nprop) atomicAdd(&a.ctl->nprop, nprop);
-    if (boundary) atomicAdd((unsigned long long*)&a.ctl->boundary, (unsigned long long)boundary);
-  }
+  flush_counts(a, evals, nprop, boundary, 0);
 }
 
-__global__ void k_begin(Ctl* ctl) {
+// ---------------------------------------------------------------------------
+// Status of every vertex at the start of a pass (with the candidate cache),
+// one thread per vertex.  A vertex is settled here when it has no candidate
+// (a clean vertex whose cached set is empty) or when the bound on the
+// change of its gains since its last exact scoring cannot make any of them
+// negative (it would not propose: its decision is written and its
+// candidates counted as scored, as the method scores them).  Every other
+// vertex goes to the rescoring list.  Also clears this pass's dirty marks
+// and the per-cluster move counts the coming apply fills.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_status(PassArgs a) {
+  Ctl* ctl = a.ctl;
   if (ctl->done) return;
+  __shared__ int32_t s_base;
+  const int par = ctl->passes & 1;
+  const int32_t* churn = a.churn + (int64_t)par * a.K0;
+  int32_t* next = a.churn + (int64_t)(par ^ 1) * a.K0;
+  const int t = threadIdx.x;
+  for (int64_t x = (int64_t)blockIdx.x * kBlock + t; x < a.K0; x += (int64_t)gridDim.x * kBlock)
+    next[x] = 0;
+  const int32_t k = a.k;
+  constexpr int V = 4;  // vertices per thread and chunk: v = c0 + j kBlock + t
+  constexpr int64_t kChunk = (int64_t)V * kBlock;
+  int64_t evals = 0, skipped = 0, boundary = 0;
+  for (int64_t c0 = (int64_t)blockIdx.x * kChunk; c0 < a.n; c0 += (int64_t)gridDim.x * kChunk) {
+    int32_t d[V], cn[V], sl[V], cv[V], stv[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int64_t v = c0 + j * kBlock + t;
+      d[j] = 1;
+      cn[j] = -1;
+      sl[j] = -1;
+      cv[j] = 0;
+      if (v < a.n) {
+        d[j] = a.dirty[v];
+        cn[j] = a.cnum[v];
+        sl[j] = a.slack[v];
+        cv[j] = a.C[v];
+      }
+    }
+    int32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int64_t v = c0 + j * kBlock + t;
+      stv[j] = -1;
+      if (v >= a.n) continue;
+      if (d[j]) a.dirty[v] = 0;  // this pass's moves mark it again
+      const int32_t cached = d[j] ? -1 : cn[j];
+      if (cached == 0) {
+        a.prop[v] = kNone;
+      } else if (cached > 0) {
+        stv[j] = cached;
+        if (sl[j] >= 0) {
+          const int4* cc = reinterpret_cast<const int4*>(a.ccache + v * kCacheCand);
+          const int4 c_lo = cc[0], c_hi = cached > 4 ? cc[1] : make_int4(0, 0, 0, 0);
+          const int32_t ids[kCacheCand] = {c_lo.x, c_lo.y, c_lo.z, c_lo.w,
+                                           c_hi.x, c_hi.y, c_hi.z, c_hi.w};
+          int32_t mx = 0;
+#pragma unroll
+          for (int q = 0; q < kCacheCand; ++q)
+            if (q < cached) mx = max(mx, churn[ids[q]]);
+          const int64_t bound = (int64_t)k * ((int64_t)churn[cv[j]] + mx);
+          if ((int64_t)sl[j] >= bound) {  // no candidate's gain can have become negative
+            a.slack[v] = (int32_t)(sl[j] - bound);
+            a.prop[v] = kNone;
+            evals += cached;
+            skipped += cached;
+            boundary += 1;
+            stv[j] = -1;
+          }
+        }
+      } else {
+        stv[j] = 0;
+      }
+      a.st[v] = stv[j];
+      mine += stv[j] >= 0;
+    }
+    // the chunk's vertices left for scoring, appended with one atomic
+    int32_t total;
+    int32_t off = block_exclusive_scan(mine, &total);
+    if (t == 0 && total) s_base = atomicAdd(&ctl->rescore_count, total);
+    __syncthreads();
+    if (total) {
+      off += s_base;
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        if (stv[j] >= 0) a.rlist[off++] = (int32_t)(c0 + j * kBlock + t);
+    }
+    __syncthreads();
+  }
+  flush_counts(a, evals, 0, boundary, skipped);
+}
+
+// ---------------------------------------------------------------------------
+// List scorer: the vertices of the rescoring list, in passes where they are
+// few, kListLanes lanes per vertex.  A vertex's candidates come from its
+// cache or from its arcs (distinct neighbour clusters, in increasing id, one
+// per lane); its own cluster and the candidates are then probed four at a
+// time with every probe of the four issued together.  Vertices with more
+// candidates than lanes, a degree beyond the arc registers or k beyond the
+// label registers go to the deferred list (the wave-per-vertex scorer).
+// ---------------------------------------------------------------------------
+constexpr int kListLanes = 16;
+
+template <int CN, int TK>
+__global__ __launch_bounds__(kBlock) void k_score_list(PassArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  const int32_t count = ctl->rescore_count;
+  if (count == 0 || count > a.sparse_max) return;  // the tiled scorer takes dense passes
+  constexpr int G = kListLanes;
+  constexpr int R = 8;               // arcs per lane in registers: degree <= 128
+  constexpr int KR = 64 / G;         // labels per lane: k <= 64
+  constexpr int32_t kInf = 0x7fffffff;
+  const int lane = threadIdx.x & (G - 1);
+  const int64_t group = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  const int64_t ngroups = ((int64_t)gridDim.x * kBlock) / G;
+  const int32_t k = a.k;
+  int64_t evals = 0;
+  int32_t nprop = 0, boundary = 0;
+  for (int64_t idx = group; idx < count; idx += ngroups) {
+    const int64_t v = a.rlist[idx];
+    const int32_t cv = a.C[v];
+    const int32_t stv = a.st[v];
+    int32_t cand = kInf, nc = 0;
+    bool defer = k > KR * G;
+    if (!defer && stv > 0) {
+      nc = stv;
+      if (lane < nc) cand = a.ccache[v * kCacheCand + lane];
+    } else if (!defer) {
+      const int64_t beg = a.row_ptr[v], end = a.row_ptr[v + 1];
+      if (end - beg > (int64_t)G * R) {
+        defer = true;
+      } else {
+        int32_t x[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int64_t j = beg + r * G + lane;
+          x[r] = kInf;
+          if (j < end) {
+            const int32_t cu = cn_load_t<CN>(a, j, CN ? a.col[j] : 0);
+            if (cu != cv) x[r] = cu;
+          }
+        }
+        for (;;) {  // distinct clusters in increasing id, candidate j on lane j
+          int32_t m = kInf;
+#pragma unroll
+          for (int r = 0; r < R; ++r) m = min(m, x[r]);
+          m = group_min<G>(m);
+          if (m == kInf) break;
+          if (nc == G) {
+            defer = true;
+            break;
+          }
+          if (lane == nc) cand = m;
+          ++nc;
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            if (x[r] == m) x[r] = kInf;
+        }
+        if (!defer) {  // the set found, cached for later passes
+          if (lane < min(nc, kCacheCand)) a.ccache[v * kCacheCand + lane] = cand;
+          if (lane == 0) a.cnum[v] = nc <= kCacheCand ? nc : -1;
+        }
+      }
+    }
+    if (defer) {
+      if (lane == 0) {
+        a.heavy[atomicAdd(&ctl->heavy_count, 1)] = (int32_t)v;
+        a.cnum[v] = -1;
+        a.slack[v] = -1;
+      }
+      continue;
+    }
+    if (nc == 0) {
+      if (lane == 0) {
+        a.prop[v] = kNone;
+        a.slack[v] = -1;
+      }
+      continue;
+    }
+    int32_t lab[KR];
+    const int32_t* row = a.Lvm + v * k;
+#pragma unroll
+    for (int t = 0; t < KR; ++t) {
+      const int i = lane + t * G;
+      lab[t] = i < k ? row[i] : 0;
+    }
+    const int64_t scv = a.s[cv];
+    int64_t s_own = 0, bd = 0;
+    int32_t bx = kNone;
+    for (int i0 = 0; i0 <= nc; i0 += 4) {  // item 0: own cluster; item j: candidate j - 1
+      int32_t part[4], ys[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int it = i0 + q;
+        const int32_t yc = __shfl(cand, it > 0 ? (it - 1) & (G - 1) : 0, G);
+        ys[q] = it == 0 ? cv : (it <= nc ? yc : -1);
+        part[q] = 0;
+        if (ys[q] >= 0) {
+#pragma unroll
+          for (int t = 0; t < KR; ++t) {
+            const int i = lane + t * G;
+            if (i < k) part[q] += count_t<TK>(a.t, i, ys[q], lab[t]);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t sum = group_sum<G>(part[q]);
+        if (ys[q] < 0) continue;
+        if (i0 + q == 0) {
+          s_own = sum;
+          continue;
+        }
+        int64_t d = 2 * (s_own - sum) + (int64_t)k * ((int64_t)a.s[ys[q]] - scv - 1);
+        if (a.literal) d += k;
+        if (bx == kNone || d < bd || (d == bd && ys[q] < bx)) {
+          bd = d;
+          bx = ys[q];
+        }
+      }
+    }
+    if (lane == 0) {
+      evals += nc;
+      boundary += 1;
+      const bool p = bd < 0;
+      a.prop[v] = p ? bx : kNone;
+      if (p) {
+        a.dprop[v] = bd;
+        ++nprop;
+      }
+      a.slack[v] = p ? -1 : (int32_t)min(bd, (int64_t)INT32_MAX);
+    }
+  }
+  flush_counts(a, evals, nprop, boundary, 0);
+}
+
+__global__ void k_begin(Ctl* ctl, int64_t* pc) {
+  if (ctl->done) return;
+  int64_t c[kPassCounters];
+#pragma unroll
+  for (int j = 0; j < kPassCounters; ++j) {
+    c[j] = pc[j * kCounterStride];
+    pc[j * kCounterStride] = 0;
+  }
+  ctl->pass_evals = c[0];
+  ctl->nprop = (int32_t)c[1];
+  ctl->boundary += c[2];
+  ctl->skipped += c[3];
   ctl->passes += 1;
   ctl->evals += ctl->pass_evals;
   ctl->pass_evals = 0;
@@ -757,9 +1032,12 @@ struct Sq2 {
   int64_t n, s;
 };
 
+// Keys: [0, cells) table cells, [cells, cells + K0) cluster sizes,
+// [cells + K0, cells + 2 K0) per-cluster move counts (churn_w).
 __device__ __attribute__((always_inline)) inline Sq2 agg_add(int32_t* hkey, int32_t* hval,
                                                            int32_t* fill, const PassArgs& a,
-                                                           int64_t key, int32_t d) {
+                                                           int32_t* churn_w, int64_t key,
+                                                           int32_t d) {
   const int32_t k32 = (int32_t)key;
   uint32_t h = ((uint32_t)k32 * 2654435761u) >> 20;  // 12 bits: kHashSlots
 #pragma unroll 1
@@ -783,8 +1061,12 @@ __device__ __attribute__((always_inline)) inline Sq2 agg_add(int32_t* hkey, int3
     const int32_t old = atomicAdd(counter(a.t, (uint32_t)key), d);
     return Sq2{2 * (int64_t)old * d + 1, 0};
   }
-  const int32_t old = atomicAdd(&a.s[key - a.cells], d);
-  return Sq2{0, 2 * (int64_t)old * d + 1};
+  if (key < a.cells + a.K0) {
+    const int32_t old = atomicAdd(&a.s[key - a.cells], d);
+    return Sq2{0, 2 * (int64_t)old * d + 1};
+  }
+  atomicAdd(&churn_w[key - a.cells - a.K0], d);
+  return Sq2{0, 0};
 }
 
 __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
@@ -804,6 +1086,9 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
   const int64_t nwaves = ((int64_t)gridDim.x * kBlock) / 64;
   int64_t dn2 = 0, ds2 = 0;
   int32_t claimed = 0;
+  // moves per cluster, read by the next pass's scorer (counted over every
+  // proposal: a fallback pass commits fewer, so the count is an upper bound)
+  int32_t* churn_w = a.churn ? a.churn + (int64_t)(ctl->passes & 1) * a.K0 : nullptr;
   // the wave serves the proposals of its 64 vertices four at a time, one
   // per group of 16 lanes, the lanes of a group spread over the partitions
   constexpr int kApplyLanes = 16;
@@ -824,14 +1109,19 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
       const int32_t* row = a.Lvm + w * a.k;
       for (int i = gl; i < a.k; i += kApplyLanes) {
         const int32_t l = row[i];
-        const Sq2 u = agg_add(hkey, hval, &fill, a, cell_upd(a.t, i, to, l, claimed), +1);
-        const Sq2 w = agg_add(hkey, hval, &fill, a, cell_upd(a.t, i, from, l, claimed), -1);
+        const Sq2 u =
+            agg_add(hkey, hval, &fill, a, churn_w, cell_upd(a.t, i, to, l, claimed), +1);
+        const Sq2 w =
+            agg_add(hkey, hval, &fill, a, churn_w, cell_upd(a.t, i, from, l, claimed), -1);
         dn2 += u.n + w.n;
       }
       if (gl == 0) {
-        const Sq2 u = agg_add(hkey, hval, &fill, a, a.cells + to, +1);
-        const Sq2 w = agg_add(hkey, hval, &fill, a, a.cells + from, -1);
+        const Sq2 u = agg_add(hkey, hval, &fill, a, churn_w, a.cells + to, +1);
+        const Sq2 w = agg_add(hkey, hval, &fill, a, churn_w, a.cells + from, -1);
         ds2 += u.s + w.s;
+      } else if (gl == 1 && churn_w) {
+        agg_add(hkey, hval, &fill, a, churn_w, a.cells + a.K0 + to, +1);
+        agg_add(hkey, hval, &fill, a, churn_w, a.cells + a.K0 + from, +1);
       }
     }
   }
@@ -842,9 +1132,11 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
     if (key < a.cells) {
       const int32_t old = atomicAdd(counter(a.t, (uint32_t)key), d);
       dn2 += 2 * (int64_t)old * d + (int64_t)d * d;
-    } else {
+    } else if (key < a.cells + a.K0) {
       const int32_t old = atomicAdd(&a.s[key - a.cells], d);
       ds2 += 2 * (int64_t)old * d + (int64_t)d * d;
+    } else {
+      atomicAdd(&churn_w[key - a.cells - a.K0], d);
     }
   }
   if (a.t.hashed) flush_claims(a.t, claimed);
@@ -1038,6 +1330,7 @@ __global__ void k_end(Ctl* ctl) {
   ctl->committed = 0;
   ctl->fallback = 0;
   ctl->heavy_count = 0;
+  ctl->rescore_count = 0;
   ctl->dS2 = 0;
   ctl->dN2 = 0;
   if (ctl->passes >= ctl->max_rounds) ctl->done = 1;
@@ -1064,6 +1357,11 @@ void launch_tile(const PassArgs& a, int grid, hipStream_t st) {
   else if (a.cn_bytes == 1) k_score_tile<1, TK><<<grid, kBlock, 0, st>>>(a);
   else if (a.cn_bytes == 2) k_score_tile<2, TK><<<grid, kBlock, 0, st>>>(a);
   else k_score_tile<4, TK><<<grid, kBlock, 0, st>>>(a);
+  if (!a.st) return;
+  if (a.ac) k_score_list<0, TK><<<grid, kBlock, 0, st>>>(a);
+  else if (a.cn_bytes == 1) k_score_list<1, TK><<<grid, kBlock, 0, st>>>(a);
+  else if (a.cn_bytes == 2) k_score_list<2, TK><<<grid, kBlock, 0, st>>>(a);
+  else k_score_list<4, TK><<<grid, kBlock, 0, st>>>(a);
 }
 
 }  // namespace
@@ -1087,6 +1385,7 @@ void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, 
   if (score_begin) (void)hipEventRecord(score_begin, st);
   switch (lanes) {
     case 0:
+      if (a.st) k_status<<<grid_apply, kBlock, 0, st>>>(a);
       if (a.t.hashed) launch_tile<kHashed>(a, grid_score, st);
       else if (a.t.interleaved) launch_tile<kInterleaved>(a, grid_score, st);
       else launch_tile<kBlocked>(a, grid_score, st);
@@ -1100,7 +1399,7 @@ void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, 
     default: launch_score<64>(a, grid_score, st); break;
   }
   if (score_end) (void)hipEventRecord(score_end, st);
-  k_begin<<<1, 1, 0, st>>>(a.ctl);
+  k_begin<<<1, 1, 0, st>>>(a.ctl, a.pc);
   if (a.t.hashed) {
     k_hash_guard<<<1, 1, 0, st>>>(a, (int64_t)((a.t.hmask + 1) / 2));
     k_hash_reset<<<grid_apply, kBlock, 0, st>>>(a);
