@@ -426,6 +426,8 @@ def main():
             "consensus_wall_ms": ms_per_step,
             "library_ms_total": sum(st["ms_total"] for st in stats) / args.steps,
             "score_kernel_ms_per_solve": score_ms,
+            "skipped_evals_per_solve": st_ref["skipped_evals"],
+            "trace": [list(r) for r in trace],
         },
         "roofline": {
             "kernel": "k_score_tile (with the deferred-vertex k_score of the same pass)",

@@ -664,6 +664,14 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
     PassArgs a{};
     a.ctl = ctl;
     a.pc = ar.get<int64_t>(kPassCounters * kCounterStride);
+    a.plist = ar.get<int32_t>(n);
+    if (!S.t.hashed) {  // histogram apply when a partition's slice fits in LDS
+      const int64_t slice = (int64_t)S.K0 * S.maxL + 2 * (int64_t)S.K0;
+      if (4 * slice <= kDeltaLdsMax) {
+        a.delta_lds = (int32_t)(4 * slice);
+        a.delta_slices = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, n / 2048));
+      }
+    }
     launch_fill_u64(reinterpret_cast<uint64_t*>(a.pc), kPassCounters * kCounterStride, 0ull, st);
     a.n = n;
     a.k = k;

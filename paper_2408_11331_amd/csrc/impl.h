@@ -33,6 +33,8 @@ struct Ctl {
   int64_t boundary;         // vertices with a candidate, summed over passes
   int32_t heavy_count;      // vertices deferred by the tiled scorer this pass
   int32_t rescore_count;    // vertices the status kernel left for scoring
+  int32_t plist_count;      // proposers of the current pass (k_props)
+  int32_t pad4;
   int64_t skipped;          // candidate evaluations proven unnecessary (all passes)
   int64_t* trace;           // device int64[max_rounds * 4] or null
 };
@@ -322,7 +324,19 @@ struct PassArgs {
   // its own 512-byte line so that their atomics do not share an L2 channel),
   // added once per workgroup and folded into the control block by k_begin.
   int64_t* pc;        // kPassCounters * kCounterStride
+  // The proposers of the pass, listed by k_props: the batch apply then runs
+  // on as many workgroups as the proposals need, so that a counter that many
+  // proposals update receives one atomic from each of few workgroups.
+  int32_t* plist;     // n
+  // Dense tables whose per-partition slice (K0 x label ids) plus two K0
+  // arrays fit kDeltaLdsMax bytes of LDS use the histogram apply
+  // (k_apply_delta) with that much dynamic LDS and delta_slices slices of
+  // the proposal list; 0: the hashed aggregation (k_apply_all).
+  int32_t delta_lds;
+  int32_t delta_slices;
 };
+
+constexpr int kDeltaLdsMax = 48 << 10;
 
 constexpr int kPassCounters = 4;    // evaluations, proposals, boundary vertices, skipped
 constexpr int kCounterStride = 64;  // int64 words between two counters

@@ -107,7 +107,9 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
   // LIST: score only the vertices the tiled scorer deferred
   const int64_t count = LIST ? (int64_t)a.ctl->heavy_count : a.n;
   if (LIST && count == 0) return;
-  constexpr int R = (128 / G) < 16 ? ((128 / G) > 1 ? (128 / G) : 1) : 16;
+  // arcs per lane held in registers; the deferred-vertex scorer (one wave
+  // per vertex) holds 512, for the highest degrees
+  constexpr int R = (LIST && G == 64) ? 8 : ((128 / G) < 16 ? ((128 / G) > 1 ? (128 / G) : 1) : 16);
   constexpr int KR = (64 / G) > 1 ? (64 / G) : 1;  // labels held per lane
   constexpr int32_t kInf = 0x7fffffff;
   __shared__ int64_t s_toff[kMaxLdsPart];
@@ -227,12 +229,17 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
         // the candidates scored four at a time by 16-lane groups, and the
         // smallest (gain, cluster id) taken by a wave reduction
         int32_t cand_lo = kInf, cand_hi = kInf, nc = 0;
+        bool many = false;  // more than 128 candidates: the general path below
         for (;;) {
           int32_t m = kInf;
 #pragma unroll
           for (int r = 0; r < R; ++r) m = min(m, x[r]);
           m = group_min<64>(m);
           if (m == kInf) break;
+          if (nc == 128) {
+            many = true;
+            break;
+          }
           if (lane == nc) cand_lo = m;
           else if (lane == nc - 64) cand_hi = m;
           ++nc;
@@ -240,84 +247,97 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
           for (int r = 0; r < R; ++r)
             if (x[r] == m) x[r] = kInf;
         }
-        if (a.dirty) {  // the candidate set, cached for later passes
-          if (lane < min(nc, kCacheCand)) a.ccache[v * kCacheCand + lane] = cand_lo;
-          if (lane == 0) a.cnum[v] = nc <= kCacheCand ? nc : -1;
-        }
-        if (nc == 0) {
-          if (lane == 0) a.prop[v] = kNone;
-          continue;
-        }
-        const int sg = lane >> 4, sl = lane & 15;
-        int32_t lb[4];  // labels of partitions sl + 16 q
+        if (!many) {
+          if (a.dirty) {  // the candidate set, cached for later passes
+            if (lane < min(nc, kCacheCand)) a.ccache[v * kCacheCand + lane] = cand_lo;
+            if (lane == 0) a.cnum[v] = nc <= kCacheCand ? nc : -1;
+          }
+          if (nc == 0) {
+            if (lane == 0) a.prop[v] = kNone;
+            continue;
+          }
+          const int sg = lane >> 4, sl = lane & 15;
+          int32_t lb[4];  // labels of partitions sl + 16 q
 #pragma unroll
-        for (int q = 0; q < 4; ++q) lb[q] = sl + 16 * q < k ? row[sl + 16 * q] : 0;
-        int32_t s_lo = 0, s_hi = 0, s_v = 0;
-        const int nitems = nc + 1;  // item 0: the own cluster; item c + 1: candidate c
-        for (int j0 = 0; j0 < nitems; j0 += 4) {
-          const int it = j0 + sg, ci = it - 1;
-          const int32_t y_lo = __shfl(cand_lo, ci < 0 ? 0 : (ci & 63), 64);
-          const int32_t y_hi = __shfl(cand_hi, ci < 0 ? 0 : (ci & 63), 64);
-          const int32_t y = it == 0 ? cv : (ci < 64 ? y_lo : y_hi);
-          int32_t sum = 0;
-          if (it < nitems) {
-            if (a.members && a.s[y] <= kMemberSumMax) {
-              const int32_t cnt = a.s[y];  // <= 16: one member id per lane
-              const int32_t mid = sl < cnt ? a.members[a.mstart[y] + sl] : 0;
-              for (int32_t mm = 0; mm < cnt; ++mm) {
-                const int32_t* ru = a.Lvm + (int64_t)__shfl(mid, mm, 16) * k;
+          for (int q = 0; q < 4; ++q) lb[q] = sl + 16 * q < k ? row[sl + 16 * q] : 0;
+          int32_t s_lo = 0, s_hi = 0, s_v = 0;
+          const int nitems = nc + 1;  // item 0: the own cluster; item c + 1: candidate c
+          for (int j0 = 0; j0 < nitems; j0 += 4) {
+            const int it = j0 + sg, ci = it - 1;
+            const int32_t y_lo = __shfl(cand_lo, ci < 0 ? 0 : (ci & 63), 64);
+            const int32_t y_hi = __shfl(cand_hi, ci < 0 ? 0 : (ci & 63), 64);
+            const int32_t y = it == 0 ? cv : (ci < 64 ? y_lo : y_hi);
+            int32_t sum = 0;
+            if (it < nitems) {
+              if (a.members && a.s[y] <= kMemberSumMax) {
+                const int32_t cnt = a.s[y];  // <= 16: one member id per lane
+                const int32_t mid = sl < cnt ? a.members[a.mstart[y] + sl] : 0;
+                for (int32_t mm = 0; mm < cnt; ++mm) {
+                  const int32_t* ru = a.Lvm + (int64_t)__shfl(mid, mm, 16) * k;
+#pragma unroll
+                  for (int q = 0; q < 4; ++q)
+                    if (sl + 16 * q < k) sum += ru[sl + 16 * q] == lb[q];
+                }
+              } else {
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                  if (sl + 16 * q < k) sum += ru[sl + 16 * q] == lb[q];
+                  if (sl + 16 * q < k) sum += count_of(a.t, sl + 16 * q, y, lb[q]);
               }
-            } else {
+            }
+            sum = group_sum<16>(sum);
+            if (j0 == 0) s_v = __shfl(sum, 0, 64);
+            const int g_lo = lane + 1 - j0, g_hi = lane + 65 - j0;  // groups holding my items
+            const int32_t got_lo = __shfl(sum, (g_lo >= 0 && g_lo < 4) ? g_lo * 16 : 0, 64);
+            const int32_t got_hi = __shfl(sum, (g_hi >= 0 && g_hi < 4) ? g_hi * 16 : 0, 64);
+            if (g_lo >= 0 && g_lo < 4) s_lo = got_lo;
+            if (g_hi >= 0 && g_hi < 4) s_hi = got_hi;
+          }
+          const int64_t scv = a.s[cv];
+          int64_t bd = INT64_MAX;
+          int32_t bx = kInf;
+          auto consider = [&](int32_t xc, int32_t sx) {
+            int64_t d = 2 * ((int64_t)s_v - sx) + (int64_t)k * ((int64_t)a.s[xc] - scv - 1);
+            if (a.literal) d += k;
+            if (d < bd || (d == bd && xc < bx)) {
+              bd = d;
+              bx = xc;
+            }
+          };
+          if (lane < nc) consider(cand_lo, s_lo);
+          if (lane + 64 < nc) consider(cand_hi, s_hi);
 #pragma unroll
-              for (int q = 0; q < 4; ++q)
-                if (sl + 16 * q < k) sum += count_of(a.t, sl + 16 * q, y, lb[q]);
+          for (int o = 32; o > 0; o >>= 1) {
+            const int64_t od = __shfl_xor(bd, o, 64);
+            const int32_t ox = __shfl_xor(bx, o, 64);
+            if (od < bd || (od == bd && ox < bx)) {
+              bd = od;
+              bx = ox;
             }
           }
-          sum = group_sum<16>(sum);
-          if (j0 == 0) s_v = __shfl(sum, 0, 64);
-          const int g_lo = lane + 1 - j0, g_hi = lane + 65 - j0;  // groups holding my items
-          const int32_t got_lo = __shfl(sum, (g_lo >= 0 && g_lo < 4) ? g_lo * 16 : 0, 64);
-          const int32_t got_hi = __shfl(sum, (g_hi >= 0 && g_hi < 4) ? g_hi * 16 : 0, 64);
-          if (g_lo >= 0 && g_lo < 4) s_lo = got_lo;
-          if (g_hi >= 0 && g_hi < 4) s_hi = got_hi;
-        }
-        const int64_t scv = a.s[cv];
-        int64_t bd = INT64_MAX;
-        int32_t bx = kInf;
-        auto consider = [&](int32_t xc, int32_t sx) {
-          int64_t d = 2 * ((int64_t)s_v - sx) + (int64_t)k * ((int64_t)a.s[xc] - scv - 1);
-          if (a.literal) d += k;
-          if (d < bd || (d == bd && xc < bx)) {
-            bd = d;
-            bx = xc;
+          if (lane == 0) {
+            evals += nc;
+            boundary += 1;
+            const bool p = bd < 0;
+            a.prop[v] = p ? bx : kNone;
+            if (p) {
+              a.dprop[v] = bd;
+              ++nprop;
+            }
+            if (a.slack) a.slack[v] = p ? -1 : (int32_t)min(bd, (int64_t)INT32_MAX);
           }
-        };
-        if (lane < nc) consider(cand_lo, s_lo);
-        if (lane + 64 < nc) consider(cand_hi, s_hi);
+          continue;
+        }
+        // the arc registers again, for the general path
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          const int64_t od = __shfl_xor(bd, o, 64);
-          const int32_t ox = __shfl_xor(bx, o, 64);
-          if (od < bd || (od == bd && ox < bx)) {
-            bd = od;
-            bx = ox;
+        for (int r = 0; r < R; ++r) {
+          const int64_t j = beg + r * G + lane;
+          x[r] = kInf;
+          if (j < end) {
+            const int32_t cu = a.ac ? a.ac[j] : cn_load(a, a.col[j]);
+            if (cu != cv) x[r] = cu;
           }
         }
-        if (lane == 0) {
-          evals += nc;
-          boundary += 1;
-          const bool p = bd < 0;
-          a.prop[v] = p ? bx : kNone;
-          if (p) {
-            a.dprop[v] = bd;
-            ++nprop;
-          }
-          if (a.slack) a.slack[v] = p ? -1 : (int32_t)min(bd, (int64_t)INT32_MAX);
-        }
-        continue;
+        if (a.dirty && lane == 0) a.cnum[v] = -1;
       }
     }
 
@@ -1069,9 +1089,43 @@ __device__ __attribute__((always_inline)) inline Sq2 agg_add(int32_t* hkey, int3
   return Sq2{0, 0};
 }
 
+// The proposers of the pass, in plist (order irrelevant): one atomic per
+// chunk of V kBlock vertices.
+__global__ __launch_bounds__(kBlock) void k_props(PassArgs a) {
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  __shared__ int32_t s_base;
+  constexpr int V = 4;
+  constexpr int64_t kChunk = (int64_t)V * kBlock;
+  const int t = threadIdx.x;
+  for (int64_t c0 = (int64_t)blockIdx.x * kChunk; c0 < a.n; c0 += (int64_t)gridDim.x * kChunk) {
+    bool pr[V];
+    int32_t mine = 0;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int64_t v = c0 + j * kBlock + t;
+      pr[j] = v < a.n && a.prop[v] >= 0;
+      mine += pr[j];
+    }
+    int32_t total;
+    int32_t off = block_exclusive_scan(mine, &total);
+    if (t == 0 && total) s_base = atomicAdd(&ctl->plist_count, total);
+    __syncthreads();
+    if (total) {
+      off += s_base;
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        if (pr[j]) a.plist[off++] = (int32_t)(c0 + j * kBlock + t);
+    }
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
   Ctl* ctl = a.ctl;
   if (ctl->done) return;
+  const int64_t count = ctl->plist_count;
+  const int64_t active = gridDim.x;
   __shared__ int32_t hkey[kHashSlots];
   __shared__ int32_t hval[kHashSlots];
   __shared__ int32_t fill;
@@ -1083,7 +1137,6 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 64;
-  const int64_t nwaves = ((int64_t)gridDim.x * kBlock) / 64;
   int64_t dn2 = 0, ds2 = 0;
   int32_t claimed = 0;
   // moves per cluster, read by the next pass's scorer (counted over every
@@ -1093,32 +1146,35 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
   // per group of 16 lanes, the lanes of a group spread over the partitions
   constexpr int kApplyLanes = 16;
   const int grp = lane / kApplyLanes, gl = lane % kApplyLanes;
-  for (int64_t v0 = wave * 64; v0 < a.n; v0 += nwaves * 64) {
-    const int64_t v = v0 + lane;
-    const int32_t p = v < a.n ? a.prop[v] : kNone;
+  // the listed proposers, 64 at a time per wave of the active workgroups
+  const int64_t nact = active * (kBlock / 64);
+  for (int64_t e0 = wave * 64; e0 < count; e0 += nact * 64) {
+    const int64_t e = e0 + lane;
+    const int32_t vl = e < count ? a.plist[e] : 0;
+    const int32_t p = e < count ? a.prop[vl] : kNone;
     uint64_t mask = __ballot(p >= 0);
     while (mask) {
-      uint64_t m = mask;  // this group's proposal: the grp-th selected vertex
+      uint64_t m = mask;  // this group's proposal: the grp-th selected entry
       for (int q = 0; q < grp; ++q) m &= m - 1;
       const int b = m ? __ffsll((unsigned long long)m) - 1 : -1;
       for (int q = 0; q < 64 / kApplyLanes; ++q) mask &= mask - 1;
       const int32_t to = __shfl(p, b < 0 ? 0 : b, 64);
+      const int64_t w = __shfl(vl, b < 0 ? 0 : b, 64);
       if (b < 0) continue;
-      const int64_t w = v0 + b;
       const int32_t from = a.C[w];
       const int32_t* row = a.Lvm + w * a.k;
       for (int i = gl; i < a.k; i += kApplyLanes) {
         const int32_t l = row[i];
-        const Sq2 u =
+        const Sq2 up =
             agg_add(hkey, hval, &fill, a, churn_w, cell_upd(a.t, i, to, l, claimed), +1);
-        const Sq2 w =
+        const Sq2 dn =
             agg_add(hkey, hval, &fill, a, churn_w, cell_upd(a.t, i, from, l, claimed), -1);
-        dn2 += u.n + w.n;
+        dn2 += up.n + dn.n;
       }
       if (gl == 0) {
-        const Sq2 u = agg_add(hkey, hval, &fill, a, churn_w, a.cells + to, +1);
-        const Sq2 w = agg_add(hkey, hval, &fill, a, churn_w, a.cells + from, -1);
-        ds2 += u.s + w.s;
+        const Sq2 up = agg_add(hkey, hval, &fill, a, churn_w, a.cells + to, +1);
+        const Sq2 dn = agg_add(hkey, hval, &fill, a, churn_w, a.cells + from, -1);
+        ds2 += up.s + dn.s;
       } else if (gl == 1 && churn_w) {
         agg_add(hkey, hval, &fill, a, churn_w, a.cells + a.K0 + to, +1);
         agg_add(hkey, hval, &fill, a, churn_w, a.cells + a.K0 + from, +1);
@@ -1145,6 +1201,123 @@ __global__ __launch_bounds__(kBlock) void k_apply_all(PassArgs a) {
   if (lane == 0) {
     if (dn2) atomicAdd((unsigned long long*)&ctl->dN2, (unsigned long long)dn2);
     if (ds2) atomicAdd((unsigned long long*)&ctl->dS2, (unsigned long long)ds2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batch apply for dense tables whose per-partition slice fits in LDS.  The
+// grid is (slices, k): workgroup (p, i) takes slice p of the listed
+// proposals and histograms partition i's count changes in LDS, +1 at
+// (to, l) and -1 at (from, l) with l the mover's label in partition i; then
+// it adds every nonzero change to the table with one atomic, whose returned
+// value gives the cell's exact share of the change of the sum of squares
+// (2 old d + d^2 for each addition, which sums to the exact change whatever
+// the order).  The workgroups of partition 0 do the same for the cluster
+// sizes and count the moves per cluster (churn).  Late passes, whose few
+// proposals mostly move between the same clusters, run one slice: each
+// counter then receives one atomic.
+// ---------------------------------------------------------------------------
+constexpr int kDeltaPerSlice = 2048;  // proposals per slice of the list
+constexpr int kDeltaUnroll = 4;
+
+template <bool IL>
+__global__ __launch_bounds__(kBlock) void k_apply_delta(PassArgs a) {
+  extern __shared__ int32_t sh[];
+  Ctl* ctl = a.ctl;
+  if (ctl->done) return;
+  const int64_t count = ctl->plist_count;
+  const int64_t active = min((int64_t)gridDim.x,
+                             max((int64_t)1, (count + kDeltaPerSlice - 1) / kDeltaPerSlice));
+  const int p = blockIdx.x, i = blockIdx.y, t = threadIdx.x;
+  if (p >= active || count == 0) return;
+  const int32_t k = a.k, K0 = a.K0;
+  const int32_t Li = IL ? a.t.Lmax : a.t.L[i];
+  const int32_t cells = K0 * Li;  // fits in LDS (checked by the host)
+  const bool sizes = i == 0;
+  int32_t* hd = sh;
+  int32_t* hs = sh + cells;
+  int32_t* hc = hs + K0;
+  const int32_t zero_len = sizes ? cells + 2 * K0 : cells;
+  for (int32_t j = t; j < zero_len; j += kBlock) sh[j] = 0;
+  __syncthreads();
+  const int64_t per = (count + active - 1) / active;
+  const int64_t eb = (int64_t)p * per, ee = min(count, eb + per);
+  for (int64_t e0 = eb + t; e0 < ee; e0 += (int64_t)kDeltaUnroll * kBlock) {
+    int32_t vv[kDeltaUnroll], to[kDeltaUnroll], fr[kDeltaUnroll], lb[kDeltaUnroll];
+#pragma unroll
+    for (int q = 0; q < kDeltaUnroll; ++q) {
+      const int64_t e = e0 + (int64_t)q * kBlock;
+      vv[q] = e < ee ? a.plist[e] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < kDeltaUnroll; ++q) {
+      if (vv[q] < 0) continue;
+      to[q] = a.prop[vv[q]];
+      fr[q] = a.C[vv[q]];
+      lb[q] = a.Lvm[(int64_t)vv[q] * k + i];
+    }
+#pragma unroll
+    for (int q = 0; q < kDeltaUnroll; ++q) {
+      if (vv[q] < 0) continue;
+      atomicAdd(&hd[to[q] * Li + lb[q]], 1);
+      atomicAdd(&hd[fr[q] * Li + lb[q]], -1);
+      if (sizes) {
+        atomicAdd(&hs[to[q]], 1);
+        atomicAdd(&hs[fr[q]], -1);
+        atomicAdd(&hc[to[q]], 1);
+        atomicAdd(&hc[fr[q]], 1);
+      }
+    }
+  }
+  __syncthreads();
+  int64_t dn2 = 0, ds2 = 0;
+  const int64_t toff = IL ? 0 : a.t.toff[i];
+  for (int32_t j0 = t; j0 < cells; j0 += kDeltaUnroll * kBlock) {
+    int32_t d[kDeltaUnroll], old[kDeltaUnroll];
+#pragma unroll
+    for (int q = 0; q < kDeltaUnroll; ++q) {
+      const int32_t j = j0 + q * kBlock;
+      d[q] = j < cells ? hd[j] : 0;
+      old[q] = 0;
+      if (d[q]) {
+        const int32_t x = j / Li, l = j - x * Li;
+        const uint32_t c = IL ? ((uint32_t)x * (uint32_t)Li + (uint32_t)l) * (uint32_t)k + i
+                              : (uint32_t)toff + (uint32_t)j;
+        old[q] = atomicAdd(&a.t.N[c], d[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kDeltaUnroll; ++q)
+      dn2 += 2 * (int64_t)old[q] * d[q] + (int64_t)d[q] * d[q];
+  }
+  if (sizes) {
+    int32_t* churn_w = a.churn ? a.churn + (int64_t)(ctl->passes & 1) * K0 : nullptr;
+    for (int32_t x = t; x < K0; x += kBlock) {
+      const int32_t d = hs[x];
+      if (d) {
+        const int32_t old = atomicAdd(&a.s[x], d);
+        ds2 += 2 * (int64_t)old * d + (int64_t)d * d;
+      }
+      if (churn_w && hc[x]) atomicAdd(&churn_w[x], hc[x]);
+    }
+  }
+  dn2 = wave_sum64(dn2);
+  ds2 = wave_sum64(ds2);
+  __shared__ int64_t red[2][kBlock / 64];
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = dn2;
+    red[1][t >> 6] = ds2;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int64_t n2 = 0, s2 = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      n2 += red[0][w];
+      s2 += red[1][w];
+    }
+    if (n2) atomicAdd((unsigned long long*)&ctl->dN2, (unsigned long long)n2);
+    if (s2) atomicAdd((unsigned long long*)&ctl->dS2, (unsigned long long)s2);
   }
 }
 
@@ -1331,6 +1504,7 @@ __global__ void k_end(Ctl* ctl) {
   ctl->fallback = 0;
   ctl->heavy_count = 0;
   ctl->rescore_count = 0;
+  ctl->plist_count = 0;
   ctl->dS2 = 0;
   ctl->dN2 = 0;
   if (ctl->passes >= ctl->max_rounds) ctl->done = 1;
@@ -1405,7 +1579,14 @@ void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, 
     k_hash_reset<<<grid_apply, kBlock, 0, st>>>(a);
     k_hash_refill<<<grid_apply, kBlock, 0, st>>>(a);
   }
-  k_apply_all<<<grid_apply, kBlock, 0, st>>>(a);
+  k_props<<<grid_apply, kBlock, 0, st>>>(a);
+  if (a.delta_lds > 0) {
+    const dim3 grid((unsigned)a.delta_slices, (unsigned)a.k);
+    if (a.t.interleaved) k_apply_delta<true><<<grid, kBlock, a.delta_lds, st>>>(a);
+    else k_apply_delta<false><<<grid, kBlock, a.delta_lds, st>>>(a);
+  } else {
+    k_apply_all<<<grid_apply, kBlock, 0, st>>>(a);
+  }
   k_decide<<<1, 1, 0, st>>>(a.ctl);
   k_apply<kCommitOrElect><<<grid_apply, kBlock, 0, st>>>(a);
   k_apply<kFallbackCommit><<<grid_apply, kBlock, 0, st>>>(a);
