@@ -59,13 +59,6 @@ def _batch_one(spec):
     return synth.sbm_batch_instance(spec)
 
 
-def _lfr_one(args):
-    import synth
-    n, k, seed = args
-    return synth.lfr(n=n, k=k, w=4 + seed, mean_deg=16.0 if n > 50_000 else 20.0,
-                     max_deg=200, min_comm=50, max_comm=1000)
-
-
 def gen_parallel(fn, items, workers=16):
     import multiprocessing as mp
     if len(items) <= 2:
@@ -155,44 +148,80 @@ def bench_batch(args):
 
 
 def bench_served(args):
-    """Config served: Poisson request stream (80% small LFR-style, 20%
-    large), rate swept; continuous batching against one solve at a time."""
-    from paper_2408_11331_amd import serve
+    """Config served: the served pool (16 LFR-style graphs of 1,000 to
+    50,000 vertices, k 4 to 16, and graphs of 200,000, 500,000 and 1,000,000
+    vertices, k 32), uploaded once; Poisson arrivals drawing small and large
+    requests 80/20; the rate swept from light load to saturation.  At each
+    rate the same arrivals are served by the continuous-batching server and
+    by one plain mcc_consensus at a time; every result of both is compared
+    with the oracle's stored result for its entry."""
+    import hashlib
+
     import numpy as np
-    rng = np.random.Generator(np.random.PCG64(20240825))
-    small = [(int(np.exp(rng.uniform(np.log(1000), np.log(50_000)))), int(rng.integers(4, 17)), j)
-             for j in range(16)]
-    large = [(n, 32, 100 + j) for j, n in enumerate(args.large_sizes)]
+
+    import synth
+    from paper_2408_11331_amd import serve
+    specs = synth.served_pool_specs(large=tuple(args.large_sizes))
     t0 = time.perf_counter()
-    insts = gen_parallel(_lfr_one, small + large)
+    insts = gen_parallel(synth.served_instance, specs)
     log(f"generated request pool ({len(insts)}) in {time.perf_counter() - t0:.1f} s")
-    pool = []
-    for i in insts:
-        pool.append(serve.Request(i.row_ptr, i.col, i.labels, i.init))
-    # 80% small / 20% large by replicating pool entries
-    weighted = [p for p in pool[:len(small)]] * 4 + [p for p in pool[len(small):]] * \
-        max(1, (4 * len(small)) // (4 * max(1, len(large))))
+    gold = None
+    gp = os.path.join(ROOT, "tests", "golden", "served_pool.json")
+    if os.path.exists(gp):
+        g = json.load(open(gp))["requests"]
+        if [r["spec"] for r in g] == specs:
+            gold = g
+            for inst, r in zip(insts, gold):
+                assert inst.digest() == r["digest"], "served pool regenerated differently"
+    pool = serve.Pool(insts)
+    weights = [0.8 / sum(not s["large"] for s in specs) if not s["large"]
+               else 0.2 / max(1, sum(s["large"] for s in specs)) for s in specs]
+
+    def sha(a):
+        return hashlib.sha256(np.ascontiguousarray(a, "<i4").tobytes()).hexdigest()
+
+    def check(reqs):
+        if gold is None:
+            return 0
+        for r in reqs:
+            assert r.error is None, r.error
+            rec = gold[r.entry]
+            assert sha(r.out) == rec["out_sha256"], f"entry {r.entry} differs from the oracle"
+            for key, val in rec["stats"].items():
+                assert r.stats[key] == val, (r.entry, key)
+        return len(reqs)
+
     rates = [float(r) for r in args.rates.split(",")]
     sweep = []
-    for rate in rates:
-        reqs, summ = serve.run_served(weighted, rate=rate, count=args.requests, seed=11,
+    checked = 0
+    for j, rate in enumerate(rates):
+        count = args.requests or int(min(600, max(60, 3 * rate)))
+        reqs, summ = serve.run_served(pool, weights, rate=rate, count=count, seed=11 + j,
                                       budget_bytes=args.budget_gib << 30)
-        base_reqs, base = serve.run_one_at_a_time(weighted, rate=rate, count=args.requests,
-                                                  seed=11)
-        same = all(np.array_equal(a.out, b.out) for a, b in zip(reqs, base_reqs))
-        sweep.append({"rate_per_s": rate, "served": summ, "one_at_a_time": base,
-                      "identical_outputs": bool(same)})
-        log(f"rate {rate}: served {summ['solves_per_s']:.1f}/s p99 {summ['p99_ms']:.1f} ms; "
-            f"plain {base['solves_per_s']:.1f}/s p99 {base['p99_ms']:.1f} ms")
+        base_reqs, base = serve.run_one_at_a_time(pool, weights, rate=rate, count=count,
+                                                  seed=11 + j)
+        checked += check(reqs) + check(base_reqs)
+        sweep.append({"rate_per_s": rate, "requests": count, "served": summ,
+                      "one_at_a_time": base})
+        log(f"rate {rate}: served {summ['solves_per_s']:.1f}/s p50 {summ['p50_ms']:.2f} "
+            f"p99 {summ['p99_ms']:.1f} ms ({summ['batches']} calls); plain "
+            f"{base['solves_per_s']:.1f}/s p50 {base['p50_ms']:.2f} p99 {base['p99_ms']:.1f} ms")
     best = max(sweep, key=lambda x: x["served"]["solves_per_s"])
+    low = sweep[0]
     return {
         "metric": "served solves/s", "value": best["served"]["solves_per_s"], "unit": "solves/s",
         "n_gpus": 1, "steps": len(rates), "warmup": 0, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": "served", "requests_per_rate": args.requests,
-                   "pool": [[i.n, i.k, i.nnz] for i in insts], "budget_gib": args.budget_gib},
+        "config": {"workload": "served", "mix": "80/20 small/large by count",
+                   "pool": [[i.n, i.k, i.nnz] for i in insts], "budget_gib": args.budget_gib,
+                   "inputs": "resident in device memory before the first request"},
+        "oracle_checked": checked,
+        "saturation_rate_per_s": best["rate_per_s"],
         "p50_ms": best["served"]["p50_ms"], "p99_ms": best["served"]["p99_ms"],
+        "lowest_rate": {"rate_per_s": low["rate_per_s"], "served_p50_ms": low["served"]["p50_ms"],
+                        "plain_p50_ms": low["one_at_a_time"]["p50_ms"]},
+        "plain_best_solves_per_s": max(x["one_at_a_time"]["solves_per_s"] for x in sweep),
         "sweep": sweep,
     }
 
@@ -303,8 +332,10 @@ def main():
                     choices=["gmm_knn", "lfr", "sbm_small", "sbm_batch", "served"])
     ap.add_argument("--count", type=int, default=0, help="sbm_batch: instances")
     ap.add_argument("--wg-per-cu", type=int, default=0, help="sbm_batch: resident workgroups")
-    ap.add_argument("--rates", default="20,80,320", help="served: arrival rates per second")
-    ap.add_argument("--requests", type=int, default=120, help="served: requests per rate")
+    ap.add_argument("--rates", default="10,20,40,80,160,320,640,1280",
+                    help="served: arrival rates per second")
+    ap.add_argument("--requests", type=int, default=0,
+                    help="served: requests per rate (0: 3 s of arrivals, 60 to 600)")
     ap.add_argument("--large-sizes", type=lambda s: [int(x) for x in s.split(",")],
                     default=[200_000, 500_000, 1_000_000], help="served: large request sizes")
     ap.add_argument("--budget-gib", type=int, default=64, help="served: HBM admission budget")

@@ -17,7 +17,9 @@
  *    caller owns every buffer; the library keeps no pointer to them after a
  *    call returns.  Its own workspace is kept between calls, per device and
  *    stream (at most 64 GiB in total; mcc_release_workspace frees it), so
- *    that repeated calls allocate nothing.
+ *    that repeated calls allocate nothing.  When an allocation fails, the
+ *    idle workspace the library keeps on that device (any stream) is freed
+ *    and the allocation tried once more before MCC_ENOMEM is returned.
  *  - `stream` is a hipStream_t passed as void*; NULL means the default
  *    stream.  Each call is stream-ordered and returns only once its results
  *    are complete (it synchronises with the stream).
@@ -129,6 +131,8 @@ typedef struct {
                               an exact bound showed the vertex could not
                               propose (with MCC_F_SYMMETRIC; they count in
                               candidate_evals as the method scores them) */
+  int64_t workspace_bytes; /* device workspace the call held (kept by the
+                              library for later calls on the stream) */
 } mcc_stats;
 
 /*
@@ -262,6 +266,9 @@ typedef struct {
   int32_t solved_in_batch; /* out: instances the persistent kernel finished
                               (the rest went through mcc_consensus) */
   float ms_total;     /* out: wall time of the call on the stream */
+  int64_t workspace_bytes; /* out: device workspace the call held at most
+                              (kept by the library for later calls on the
+                              stream) */
 } mcc_batch_opts;
 
 /*
@@ -309,6 +316,40 @@ int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stat
  */
 int mcc_batch_tune(const mcc_problem* probs, int32_t count, const mcc_batch_opts* opts,
                    mcc_tune_table* table);
+
+/*
+ * Device memory budgeting (for callers that admit work by memory, such as
+ * a server).  Host only; nothing is launched or allocated.
+ *
+ * mcc_workspace_bound: an upper bound of the workspace mcc_consensus takes
+ * for an instance of n vertices, nnz arcs and k partitions whose label
+ * values all lie in [0, max_label], started from an init with `clusters`
+ * distinct ids (0: unknown, or singletons), with these flags: every array
+ * it sizes from those figures (the contingency tables at the largest size
+ * the layouts that can be chosen may take), arrays below the 16 MiB chunk
+ * size counted twice for the chunk ends they may leave unused, plus one
+ * chunk.  The exact figure of a finished call is stats->workspace_bytes.
+ *
+ * mcc_batch_workspace_bytes: the workspace of one mcc_consensus_batch call
+ * over these problems and options: the persistent launch's slots as the
+ * call would size them (twice over for chunking, plus one chunk), or the
+ * bound of the largest instance the call hands to mcc_consensus if that is
+ * larger (instances with k > 256; instances that turn out to exceed a
+ * slot's table are not foreseen).  The exact figure of a finished call is
+ * opts->workspace_bytes.
+ *
+ * mcc_workspace_held: the workspace the library keeps, between calls, for
+ * `stream` on the current device (0 if none): what calls on that stream
+ * hold when idle.
+ *
+ * All three return 0 or MCC_EINVAL (NULL bytes, sizes out of range);
+ * mcc_workspace_held may return MCC_EDEVICE.
+ */
+int mcc_workspace_bound(int64_t n, int64_t nnz, int32_t k, int64_t max_label, int64_t clusters,
+                        uint32_t flags, int64_t* bytes);
+int mcc_batch_workspace_bytes(const mcc_problem* probs, int32_t count,
+                              const mcc_batch_opts* opts, int64_t* bytes);
+int mcc_workspace_held(void* stream, int64_t* bytes);
 
 /* Write a tune table as text to `path` / read it back.  Host only.
  * Returns 0, MCC_EINVAL (NULL argument, unreadable or malformed file,
@@ -384,8 +425,8 @@ int mcc_group_partitions(const int32_t* const* labels, int32_t k, int64_t n, int
                          void* stream);
 
 /* Free the workspace the library keeps between calls (every device and
- * stream).  Call it with no other libmcc call in flight.  Returns 0 or
- * MCC_EDEVICE. */
+ * stream), and the batched launch's graphs.  Call it with no other libmcc
+ * call in flight.  Returns 0 or MCC_EDEVICE. */
 int mcc_release_workspace(void);
 
 /* Static text for a return code (for MCC_EDEVICE, the last HIP error seen

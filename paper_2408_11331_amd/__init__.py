@@ -23,7 +23,8 @@ MCC_F_ARC_CACHE, MCC_F_HASH_TABLES, MCC_F_SYMMETRIC = 0x10, 0x20, 0x40
 EXPORTS = ("mcc_consensus", "mcc_consensus_noalloc", "mcc_objective", "mcc_mirkin", "mcc_canonicalize",
            "mcc_consensus_batch", "mcc_batch_tune", "mcc_tune_save", "mcc_tune_load",
            "mcc_compare", "mcc_split_join_matrix", "mcc_group_from_distances",
-           "mcc_group_partitions", "mcc_release_workspace", "mcc_strerror")
+           "mcc_group_partitions", "mcc_release_workspace", "mcc_workspace_bound",
+           "mcc_batch_workspace_bytes", "mcc_workspace_held", "mcc_strerror")
 MCC_TUNE_LANES, MCC_TUNE_MAX_BUCKETS = 5, 160
 TUNE_LANES = (4, 8, 16, 32, 64)
 
@@ -45,12 +46,12 @@ class Stats(ctypes.Structure):
         ("ms_total", ctypes.c_float), ("ms_passes", ctypes.c_float),
         ("boundary", ctypes.c_int64), ("ms_score", ctypes.c_float),
         ("lanes_used", ctypes.c_int32), ("tables", ctypes.c_int32),
-        ("skipped_evals", ctypes.c_int64),
+        ("skipped_evals", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
     ]
 
     OUT = ("passes", "converged", "fallback_rounds", "clusters", "moves", "candidate_evals",
            "objective_init", "objective", "ms_total", "ms_passes", "boundary", "ms_score",
-           "lanes_used", "tables", "skipped_evals")
+           "lanes_used", "tables", "skipped_evals", "workspace_bytes")
 
     def as_dict(self):
         return {f: getattr(self, f) for f in self.OUT}
@@ -95,7 +96,8 @@ class BatchOpts(ctypes.Structure):
                 ("flags", ctypes.c_uint32), ("lanes", ctypes.c_int32),
                 ("wg_per_cu", ctypes.c_int32), ("status", ctypes.c_void_p),
                 ("tune", ctypes.c_void_p), ("tune_cache_path", ctypes.c_char_p),
-                ("solved_in_batch", ctypes.c_int32), ("ms_total", ctypes.c_float)]
+                ("solved_in_batch", ctypes.c_int32), ("ms_total", ctypes.c_float),
+                ("workspace_bytes", ctypes.c_int64)]
 
 
 class MccError(RuntimeError):
@@ -137,6 +139,13 @@ def lib():
         L.mcc_group_from_distances.argtypes = [p, i32, i64, p, p, p]
         L.mcc_group_partitions.argtypes = [p, i32, i64, i64, p, p, p, p, p]
         L.mcc_release_workspace.argtypes = []
+        L.mcc_workspace_bound.argtypes = [i64, i64, i32, i64, i64, ctypes.c_uint32, p]
+        L.mcc_workspace_bound.restype = ctypes.c_int
+        L.mcc_batch_workspace_bytes.argtypes = [ctypes.POINTER(Problem), i32,
+                                                ctypes.POINTER(BatchOpts), p]
+        L.mcc_batch_workspace_bytes.restype = ctypes.c_int
+        L.mcc_workspace_held.argtypes = [p, p]
+        L.mcc_workspace_held.restype = ctypes.c_int
         for f in ("mcc_compare", "mcc_split_join_matrix", "mcc_group_from_distances",
                   "mcc_group_partitions", "mcc_release_workspace"):
             getattr(L, f).restype = ctypes.c_int
@@ -325,7 +334,8 @@ def consensus_batch(problems, *, max_rounds=0, flags=0, lanes=0, wg_per_cu=0, st
     if rc not in (0, MCC_EINVAL):
         _check(rc)
     return outs, [st[j].as_dict() for j in range(count)], codes, \
-        {"solved_in_batch": o.solved_in_batch, "ms_total": o.ms_total, "rc": rc}
+        {"solved_in_batch": o.solved_in_batch, "ms_total": o.ms_total, "rc": rc,
+         "workspace_bytes": o.workspace_bytes}
 
 
 def batch_tune(problems, *, max_rounds=0, flags=0, wg_per_cu=0, stream=None,
@@ -431,6 +441,33 @@ def consensus_groups(row_ptr, col, labels, lam=-1, init="first", max_rounds=0, f
     return g, used, outs, stats
 
 
+def workspace_bound(n, nnz, k, max_label, clusters=0, flags=0) -> int:
+    """Upper bound of the device workspace of one solve of that size (host)."""
+    b = ctypes.c_int64(0)
+    _check(lib().mcc_workspace_bound(int(n), int(nnz), int(k), int(max_label), int(clusters),
+                                     int(flags), ctypes.byref(b)))
+    return b.value
+
+
+def batch_workspace_bytes(problems, *, lanes=0, wg_per_cu=0, tune=None, tune_cache_path=None) -> int:
+    """Device workspace of one batched call over these problems (host)."""
+    arr, keep = _problems(problems, None)
+    o = BatchOpts()
+    o.lanes, o.wg_per_cu = lanes, wg_per_cu
+    o.tune = ctypes.cast(ctypes.pointer(tune), ctypes.c_void_p) if tune is not None else None
+    o.tune_cache_path = tune_cache_path.encode() if tune_cache_path else None
+    b = ctypes.c_int64(0)
+    _check(lib().mcc_batch_workspace_bytes(arr, len(problems), ctypes.byref(o), ctypes.byref(b)))
+    return b.value
+
+
+def workspace_held(stream=None) -> int:
+    """Workspace the library keeps between calls for this stream (host)."""
+    b = ctypes.c_int64(0)
+    _check(lib().mcc_workspace_held(_stream_ptr(stream), ctypes.byref(b)))
+    return b.value
+
+
 def release_workspace():
     """Free the device workspace the library keeps between calls."""
     _check(lib().mcc_release_workspace())
@@ -528,4 +565,5 @@ def consensus_batch_packed(pb, *, max_rounds=0, flags=0, lanes=0, wg_per_cu=0, s
     rc = lib().mcc_consensus_batch(recs, pb.count, pb.stats, ctypes.byref(o))
     if rc not in (0, MCC_EINVAL):
         _check(rc)
-    return {"solved_in_batch": o.solved_in_batch, "ms_total": o.ms_total, "rc": rc}
+    return {"solved_in_batch": o.solved_in_batch, "ms_total": o.ms_total, "rc": rc,
+            "workspace_bytes": o.workspace_bytes}

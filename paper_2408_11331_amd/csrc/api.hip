@@ -51,12 +51,14 @@ struct Status {
   int code;
 };
 
-// Workspace chunks kept between calls, per (device, stream): a call takes the
-// chunks its stream left and gives them back when it returns, so steady-state
-// calls allocate and free nothing (allocation and free calls cost about a
-// tenth of a millisecond each).  Reuse on the same stream is ordered by the
-// stream.  Chunks beyond kCachedMax bytes in total are freed on return;
-// mcc_release_workspace frees the rest.
+// Workspace chunks kept between calls, per (device, stream): an arena takes
+// a cached chunk of its stream when it needs one and gives back what it took
+// when it ends, so steady-state calls allocate and free nothing (allocation
+// and free calls cost about a tenth of a millisecond each), and arenas
+// nested on one stream share the cache instead of each allocating anew.
+// Reuse on the same stream is ordered by the stream.  Chunks beyond
+// kCachedMax bytes in total are freed on return; mcc_release_workspace frees
+// the rest.
 struct Chunk {
   void* p;
   size_t size;
@@ -75,36 +77,57 @@ ChunkCache& chunk_cache() {
 
 constexpr size_t kCachedMax = (size_t)64 << 30;
 
+// Frees the cached (idle) chunks of device `dev`, which is current.
+void release_cached(int dev) {
+  ChunkCache& c = chunk_cache();
+  std::lock_guard<std::mutex> lock(c.m);
+  for (auto it = c.free.begin(); it != c.free.end();) {
+    if (it->first.first != dev) {
+      ++it;
+      continue;
+    }
+    for (const Chunk& k : it->second) {
+      (void)hipFree(k.p);
+      c.bytes -= k.size;
+    }
+    it = c.free.erase(it);
+  }
+}
+
 class Arena {
  public:
-  explicit Arena(hipStream_t st) : st_(st) {
-    (void)hipGetDevice(&dev_);
-    take_cached();
-  }
+  explicit Arena(hipStream_t st) : st_(st) { (void)hipGetDevice(&dev_); }
   // An arena over a fixed device region of `cap` bytes: get() carves from
   // it and throws Status{MCC_ESCRATCH} when it is full; nothing is
   // allocated, freed or cached.
   Arena(hipStream_t st, unsigned char* fixed, size_t cap)
-      : st_(st), fixed_(fixed != nullptr), next_(fixed), left_(fixed ? cap : 0) {
+      : st_(st), fixed_(fixed != nullptr), next_(fixed), left_(fixed ? cap : 0),
+        fixed_cap_(fixed ? cap : 0) {
     (void)hipGetDevice(&dev_);
-    if (!fixed_) take_cached();
   }
   ~Arena() {
     // kernels and queued copies may still use the chunks: drain first
     (void)hipStreamSynchronize(st_);
-    if (fixed_) return;
+    if (fixed_ || used_.empty()) return;
     ChunkCache& c = chunk_cache();
     std::lock_guard<std::mutex> lock(c.m);
     std::vector<Chunk>& keep = c.free[{dev_, st_}];
-    for (std::vector<Chunk>* list : {&used_, &avail_})
-      for (const Chunk& k : *list) {
-        if (c.bytes + k.size <= kCachedMax) {
-          keep.push_back(k);
-          c.bytes += k.size;
-        } else {
-          (void)hipFree(k.p);
-        }
+    for (const Chunk& k : used_) {
+      if (c.bytes + k.size <= kCachedMax) {
+        keep.push_back(k);
+        c.bytes += k.size;
+      } else {
+        (void)hipFree(k.p);
       }
+    }
+  }
+  // Device bytes the arena holds: the chunks taken, or the fixed region's
+  // carved part.
+  size_t bytes_used() const {
+    if (fixed_) return fixed_cap_ - left_;
+    size_t b = 0;
+    for (const Chunk& k : used_) b += k.size;
+    return b;
   }
   // Host buffer that lives as long as the arena (source of async copies).
   template <class T>
@@ -135,32 +158,39 @@ class Arena {
   }
 
  private:
-  void take_cached() {
-    ChunkCache& c = chunk_cache();
-    std::lock_guard<std::mutex> lock(c.m);
-    auto it = c.free.find({dev_, st_});
-    if (it != c.free.end()) {
-      avail_.swap(it->second);
-      for (const Chunk& k : avail_) c.bytes -= k.size;
-      c.free.erase(it);
-    }
-  }
-  // The smallest cached chunk of at least `size` bytes, else a new one.
+  // The smallest cached chunk of the stream of at least `size` bytes, else
+  // a new one.
   Chunk chunk(size_t size) {
-    size_t best = avail_.size();
-    for (size_t j = 0; j < avail_.size(); ++j)
-      if (avail_[j].size >= size && (best == avail_.size() || avail_[j].size < avail_[best].size))
-        best = j;
-    Chunk k;
-    if (best < avail_.size()) {
-      k = avail_[best];
-      avail_.erase(avail_.begin() + best);
-    } else {
+    Chunk k{nullptr, 0};
+    {
+      ChunkCache& c = chunk_cache();
+      std::lock_guard<std::mutex> lock(c.m);
+      auto it = c.free.find({dev_, st_});
+      if (it != c.free.end()) {
+        std::vector<Chunk>& v = it->second;
+        size_t best = v.size();
+        for (size_t j = 0; j < v.size(); ++j)
+          if (v[j].size >= size && (best == v.size() || v[j].size < v[best].size)) best = j;
+        if (best < v.size()) {
+          k = v[best];
+          v.erase(v.begin() + best);
+          c.bytes -= k.size;
+          if (v.empty()) c.free.erase(it);
+        }
+      }
+    }
+    if (!k.p) {
       void* p = nullptr;
       hipError_t e = hipMalloc(&p, size);
       if (e == hipErrorOutOfMemory) {
+        // free every idle cached chunk of the device (any stream) and retry once
         (void)hipGetLastError();
-        throw NoMem{};
+        release_cached(dev_);
+        e = hipMalloc(&p, size);
+        if (e == hipErrorOutOfMemory) {
+          (void)hipGetLastError();
+          throw NoMem{};
+        }
       }
       hipck(e, "hipMalloc");
       k = {p, size};
@@ -173,9 +203,10 @@ class Arena {
   hipStream_t st_;
   bool fixed_ = false;
   int dev_ = 0;
-  std::vector<Chunk> used_, avail_;
+  std::vector<Chunk> used_;
   unsigned char* next_ = nullptr;
   size_t left_ = 0;
+  size_t fixed_cap_ = 0;
   std::vector<std::vector<unsigned char>> staging_;
 };
 
@@ -595,6 +626,7 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
     stats->lanes_used = 0;
     stats->tables = 0;
     stats->skipped_evals = 0;
+    stats->workspace_bytes = 0;
   }
   if (n == 0) {
     if (stats) {
@@ -803,6 +835,7 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
       stats->moves = hc.moves;
       stats->candidate_evals = hc.evals;
       stats->skipped_evals = hc.skipped;
+      stats->workspace_bytes = (int64_t)ar.bytes_used();
       stats->objective_init = (int64_t)k * acc[0] + acc[1] - 2 * acc[2];
       stats->objective = hc.O;
       float ms = 0.f;
@@ -1008,6 +1041,116 @@ bool problem_ok(const mcc_problem& p, bool need_out, VisibleRanges& vis) {
   return ok;
 }
 
+// The persistent launch as a one-node HIP graph per (device, stream),
+// instantiated once and replayed: each call sets the node's arguments and
+// grid.  Its queue counter lives with it (never reset; see BatchArgs).
+struct BatchGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t node = nullptr;
+  unsigned long long* queue = nullptr;
+  unsigned long long qnext = 0;
+};
+
+struct GraphCache {
+  std::mutex m;
+  std::map<std::pair<int, hipStream_t>, BatchGraph> g;
+};
+
+GraphCache& graph_cache() {
+  static GraphCache* c = new GraphCache;  // never destroyed: may outlive static teardown
+  return *c;
+}
+
+void destroy_graph(BatchGraph& bg) {
+  if (bg.exec) (void)hipGraphExecDestroy(bg.exec);
+  if (bg.graph) (void)hipGraphDestroy(bg.graph);
+  if (bg.queue) (void)hipFree(bg.queue);
+  bg = BatchGraph{};
+}
+
+// Launch the persistent kernel over `ba` (ba.queue and ba.qbase are filled
+// here) through the stream's graph, bracketed by the two events.
+void launch_batch_graph(BatchArgs& ba, int grid, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  int dev = 0;
+  HIPCK(hipGetDevice(&dev));
+  GraphCache& c = graph_cache();
+  std::lock_guard<std::mutex> lock(c.m);
+  BatchGraph& bg = c.g[{dev, st}];
+  if (!bg.queue) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(unsigned long long));
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      throw NoMem{};
+    }
+    hipck(e, "hipMalloc");
+    bg.queue = static_cast<unsigned long long*>(q);
+    launch_fill_u64(reinterpret_cast<uint64_t*>(bg.queue), 1, 0ull, st);
+    bg.qnext = 0;
+  }
+  ba.queue = bg.queue;
+  ba.qbase = bg.qnext;
+  void* args[] = {&ba};
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(batch_kernel());
+  kp.gridDim = dim3((unsigned)grid);
+  kp.blockDim = dim3(kBlock);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  hipError_t e = hipSuccess;
+  if (!bg.exec) {
+    e = hipGraphCreate(&bg.graph, 0);
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&bg.node, bg.graph, nullptr, 0, &kp);
+    if (e == hipSuccess) e = hipGraphInstantiate(&bg.exec, bg.graph, nullptr, nullptr, 0);
+  } else {
+    e = hipGraphExecKernelNodeSetParams(bg.exec, bg.node, &kp);
+  }
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  if (e == hipSuccess) e = hipGraphLaunch(bg.exec, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e != hipSuccess) {  // the counter may be out of step: start over next time
+    destroy_graph(bg);
+    c.g.erase({dev, st});
+    HIPCK(e);
+  }
+  bg.qnext += (unsigned long long)ba.count + (unsigned long long)grid;
+}
+
+// Sizes of the persistent launch's workspace for a set of problems.
+struct BatchSizes {
+  int64_t n_max = 1;
+  int32_t k_max = 1;
+  int64_t slots = 1;
+  int64_t labels = 0;  // label pointers
+  int64_t bytes = 0;   // device bytes, allocation by allocation as the arena rounds them
+};
+
+int64_t arena_round(int64_t bytes) { return (std::max<int64_t>(bytes, 1) + 255) & ~(int64_t)255; }
+
+BatchSizes batch_sizes(const mcc_problem* probs, const std::vector<int32_t>& ids, int32_t count,
+                       int64_t cells_cap, int wgpc) {
+  BatchSizes z;
+  for (int32_t i : ids) {
+    z.labels += probs[i].k;
+    z.n_max = std::max<int64_t>(z.n_max, probs[i].g.n);
+    z.k_max = std::max<int32_t>(z.k_max, probs[i].k);
+  }
+  z.slots = std::max<int64_t>(1, std::min<int64_t>((int64_t)ids.size(),
+                                                   (int64_t)device_sms() * wgpc));
+  const int64_t flag_cap = 2 * z.n_max + 1024;
+  z.bytes = arena_round(8 * std::max<int64_t>(1, z.labels)) +
+            4 * arena_round(4 * z.slots * z.n_max) +            // C, rawid, prop, s
+            2 * arena_round(8 * z.slots * z.n_max) +            // dprop, owner
+            arena_round(4 * z.slots * z.n_max * z.k_max) +      // label rows
+            arena_round(4 * z.slots * cells_cap) +              // tables
+            arena_round(4 * z.slots * flag_cap) +               // flags
+            arena_round((int64_t)sizeof(BatchInst) * count) + arena_round(4 * (int64_t)ids.size()) +
+            arena_round((int64_t)sizeof(BatchRes) * count);
+  return z;
+}
+
 struct BatchRun {
   const mcc_problem* probs = nullptr;
   std::vector<int32_t> ids;      // problems to run
@@ -1017,12 +1160,12 @@ struct BatchRun {
   int64_t cells_cap = 0;
   int32_t max_rounds = 1000;
   int32_t literal = 0;
-  bool capture = false;
 };
 
 // One persistent launch over run.ids; per-problem results land in hres
 // (indexed like probs); returns the launch's time on the stream in ms.
-float run_batch(const BatchRun& run, int32_t count, hipStream_t st, std::vector<BatchRes>* hres) {
+float run_batch(const BatchRun& run, int32_t count, hipStream_t st, std::vector<BatchRes>* hres,
+                int64_t* ws_bytes = nullptr) {
   Arena ar(st);  // the launch's workspace, released on return
   const mcc_problem* probs = run.probs;
   std::vector<const int32_t*> allptr;
@@ -1080,11 +1223,9 @@ float run_batch(const BatchRun& run, int32_t count, hipStream_t st, std::vector<
   int32_t* dorder = ar.get<int32_t>((int64_t)order.size());
   h2d(dorder, ar.host(order), (int64_t)order.size(), st);
   BatchRes* dres = ar.get<BatchRes>(count);
-  int32_t* dqueue = ar.get<int32_t>(1);
   ba.inst = dinst;
   ba.order = dorder;
   ba.res = dres;
-  ba.queue = dqueue;
   ba.count = (int32_t)order.size();
   ba.max_rounds = run.max_rounds;
   ba.literal = run.literal;
@@ -1098,34 +1239,13 @@ float run_batch(const BatchRun& run, int32_t count, hipStream_t st, std::vector<
       (void)hipEventDestroy(b);
     }
   } evg{e0, e1};
-  // the queue reset and the persistent kernel, as one captured graph
-  // (the legacy default stream cannot be captured: plain launches there)
-  if (run.capture && st) {
-    sync(st);
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    HIPCK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    launch_fill_i32(dqueue, 1, 0, st);
-    launch_batch(ba, (int)slots, st);
-    hipError_t ce = hipStreamEndCapture(st, &graph);
-    if (ce == hipSuccess) ce = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (ce == hipSuccess) ce = hipEventRecord(e0, st);
-    if (ce == hipSuccess) ce = hipGraphLaunch(exec, st);
-    if (ce == hipSuccess) ce = hipEventRecord(e1, st);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    HIPCK(ce);
-  } else {
-    launch_fill_i32(dqueue, 1, 0, st);
-    HIPCK(hipEventRecord(e0, st));
-    launch_batch(ba, (int)slots, st);
-    HIPCK(hipEventRecord(e1, st));
-  }
+  launch_batch_graph(ba, (int)slots, st, e0, e1);
   hres->assign(count, BatchRes{});
   d2h(hres->data(), dres, count, st);
   sync(st);
   float ms = 0.f;
   HIPCK(hipEventElapsedTime(&ms, e0, e1));
+  if (ws_bytes) *ws_bytes = (int64_t)ar.bytes_used();
   return ms;
 }
 
@@ -1165,6 +1285,7 @@ int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stat
   if (opts) {
     opts->solved_in_batch = 0;
     opts->ms_total = 0.f;
+    opts->workspace_bytes = 0;
   }
   if (count == 0) return MCC_OK;
 
@@ -1183,7 +1304,6 @@ int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stat
 
   int first_err = MCC_OK;
   try {
-    Arena ar(st);
     hipEvent_t e0, e1;
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
@@ -1214,8 +1334,9 @@ int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stat
       run.wgpc = wgpc;
       run.max_rounds = max_rounds;
       run.literal = (flags & MCC_F_LITERAL) ? 1 : 0;
-      run.capture = true;
-      run_batch(run, count, st, &hres);
+      int64_t ws = 0;
+      run_batch(run, count, st, &hres, &ws);
+      if (opts) opts->workspace_bytes = ws;
       for (int32_t i : eligible) {
         if (hres[i].status == kBatchTooBig) fallback.push_back(i);
         else if (hres[i].status == kBatchInvalid) status[i] = MCC_EINVAL;
@@ -1245,6 +1366,7 @@ int mcc_consensus_batch(const mcc_problem* probs, int32_t count, mcc_stats* stat
       const int rc = mcc_consensus(&p.g, p.labels, p.k, p.init, p.out, &one);
       status[i] = rc;
       if (stats && rc == MCC_OK) stats[i] = one;
+      if (opts) opts->workspace_bytes = std::max(opts->workspace_bytes, one.workspace_bytes);
     }
     HIPCK(hipEventRecord(e1, st));
     sync(st);
@@ -1640,6 +1762,12 @@ int mcc_group_partitions(const int32_t* const* labels, int32_t k, int64_t n, int
 }
 
 int mcc_release_workspace(void) {
+  {
+    GraphCache& g = graph_cache();
+    std::lock_guard<std::mutex> lock(g.m);
+    for (auto& kv : g.g) destroy_graph(kv.second);
+    g.g.clear();
+  }
   ChunkCache& c = chunk_cache();
   std::lock_guard<std::mutex> lock(c.m);
   int cur = 0;
@@ -1654,6 +1782,140 @@ int mcc_release_workspace(void) {
   c.bytes = 0;
   (void)hipSetDevice(cur);
   return rc;
+}
+
+int mcc_workspace_held(void* stream, int64_t* bytes) {
+  if (!bytes) return MCC_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MCC_EDEVICE;
+  ChunkCache& c = chunk_cache();
+  std::lock_guard<std::mutex> lock(c.m);
+  int64_t b = 0;
+  auto it = c.free.find({dev, (hipStream_t)stream});
+  if (it != c.free.end())
+    for (const Chunk& k : it->second) b += (int64_t)k.size;
+  *bytes = b;
+  return MCC_OK;
+}
+
+int mcc_workspace_bound(int64_t n, int64_t nnz, int32_t k, int64_t max_label, int64_t clusters,
+                        uint32_t flags, int64_t* bytes) {
+  if (!bytes || n < 0 || nnz < 0 || k < 1 || max_label < 0) return MCC_EINVAL;
+  if ((int64_t)k * n >= ((int64_t)1 << 31)) return MCC_EINVAL;
+  const int64_t nk = n * (int64_t)k;
+  const int64_t span = std::min<int64_t>((int64_t)k * (max_label + 1), kMaxLabelFlags);
+  const int64_t K0 = clusters > 0 ? std::min(clusters, n) : n;
+  const int64_t sumL = std::min<int64_t>(span, nk);
+  constexpr int64_t kChunk = (int64_t)16 << 20;
+  // requests below a chunk are carved from chunks (at most as much again is
+  // lost at chunk ends), larger ones get chunks of their own
+  int64_t small = 0, big = 0;
+  auto add = [&](int64_t b) {
+    b = arena_round(b);
+    if (b < kChunk) small += b;
+    else big += b;
+  };
+  // labels and clusters: flags, scans, maps, row pointers
+  add(4); add(8 * k); add(4 * k); add(8 * (k + 1));
+  for (int j = 0; j < 3; ++j) add(4 * (span + 1));
+  add(4 * (scan_tmp_elems(span) + 1)); add(4 * k);
+  add(4 * (n + 1)); add(4 * (n + 1)); add(4 * (scan_tmp_elems(n) + 1));
+  add(4 * n); add(4 * K0); add(4 * K0);
+  // tables: the dense layouts (blocked, alignment, interleaved) when they
+  // can be chosen, the hashed table when it can
+  const int64_t dense_cap = std::max<int64_t>((int64_t)1 << 24, 16 * nk);
+  const int64_t dense_ub = K0 * sumL;  // clusters x labels, at most
+  const bool can_hash = dense_ub > std::min<int64_t>(kMaxTableEntries, dense_cap);
+  const int64_t dense = std::min<int64_t>(dense_ub, std::min<int64_t>(kMaxTableEntries, dense_cap));
+  int64_t dsmall = 0, dbig = 0, hsmall = 0, hbig = 0;
+  {
+    std::swap(small, dsmall);
+    std::swap(big, dbig);
+    add(8 * (k + 1)); add(4 * dense);
+    if (K0 <= (1 << 16)) {
+      add(8 * k * K0);
+      for (int j = 0; j < 3; ++j) add(4 * (sumL + 1));
+      add(8 * sumL); add(4 * sumL); add(4 * (scan_tmp_elems(sumL) + 1)); add(4 * k);
+      add(4 * std::min<int64_t>(kMaxTableEntries, 2 * dense + (1 << 20)));
+    }
+    std::swap(small, dsmall);
+    std::swap(big, dbig);
+  }
+  if (can_hash) {
+    std::swap(small, hsmall);
+    std::swap(big, hbig);
+    int bits = 12;
+    while (((int64_t)1 << bits) < 4 * nk) ++bits;
+    add(8 * (k + 1)); add(16 * ((int64_t)1 << bits)); add(8); add(4 * sumL);
+    add(4 * (K0 + 1)); add(4 * K0); add(4 * n); add(4 * (scan_tmp_elems(K0) + 1));
+    std::swap(small, hsmall);
+    std::swap(big, hbig);
+  }
+  if (2 * hsmall + hbig > 2 * dsmall + dbig) {
+    small += hsmall;
+    big += hbig;
+  } else {
+    small += dsmall;
+    big += dbig;
+  }
+  add(4 * nk); add(24);  // label rows, objective sums
+  // per-pass state
+  add(sizeof(Ctl)); add(8 * K0); add(4 * n); add(8 * n); add(4 * n); add(4 * n);
+  add(8 * kPassCounters * kCounterStride); add(2 * n); add(4); add(4);
+  if (flags & MCC_F_TRACE) add(8 * 4 * 1000);
+  if (flags & MCC_F_ARC_CACHE) {
+    add(4 * (n + 1)); add(4 * (n + 1)); add(4 * (scan_tmp_elems(n) + 1));
+    add(4 * nnz); add(4 * nnz);
+  }
+  if (flags & MCC_F_SYMMETRIC) {
+    for (int j = 0; j < 5; ++j) add(4 * n);
+    add(4 * n * kCacheCand); add(8 * K0); add(4);
+  }
+  *bytes = big + 2 * small + kChunk;
+  return MCC_OK;
+}
+
+int mcc_batch_workspace_bytes(const mcc_problem* probs, int32_t count,
+                              const mcc_batch_opts* opts, int64_t* bytes) {
+  if (!bytes || count < 0 || (count > 0 && !probs)) return MCC_EINVAL;
+  *bytes = 0;
+  const int lanes = opts ? opts->lanes : 0;
+  if (!batch_lanes_ok(lanes)) return MCC_EINVAL;
+  const mcc_tune_table* table = opts ? opts->tune : nullptr;
+  mcc_tune_table loaded;
+  if (!table && lanes == 0 && opts && opts->tune_cache_path &&
+      mcc_tune_load(&loaded, opts->tune_cache_path) == MCC_OK)
+    table = &loaded;
+  int wgpc = opts && opts->wg_per_cu > 0 ? opts->wg_per_cu : (table ? table->wg_per_cu : 2);
+  wgpc = std::max(1, std::min(wgpc, 8));
+  std::vector<int32_t> eligible;
+  int64_t single = 0;  // the largest bound of an instance solved by mcc_consensus
+  for (int32_t i = 0; i < count; ++i) {
+    const mcc_problem& p = probs[i];
+    if (p.k < 1 || p.g.n < 0 || (int64_t)p.k * p.g.n >= ((int64_t)1 << 31)) return MCC_EINVAL;
+    int64_t bound = 0;
+    const int rc = mcc_workspace_bound(p.g.n, p.g.nnz, p.k, std::max<int64_t>(0, p.g.n - 1),
+                                       0, 0, &bound);
+    if (rc) return rc;
+    if (p.k > 256) single = std::max(single, bound);
+    else eligible.push_back(i);
+  }
+  if (!eligible.empty()) {
+    int64_t cells = 0;
+    bool covered = table != nullptr;
+    for (int32_t i : eligible) {
+      const mcc_tune_entry* e = tune_lookup(table, probs[i].g.n, probs[i].k);
+      if (!e) covered = false;
+      else cells = std::max(cells, e->cells);
+    }
+    const int64_t cap = covered ? std::min(kCellsCapMax, std::max(kCellsCapMin, pow2_ceil(cells)))
+                                : heuristic_cells_cap(probs, eligible);
+    const BatchSizes z = batch_sizes(probs, eligible, count, cap, wgpc);
+    // carved from 16 MiB chunks (larger requests get their own)
+    *bytes = 2 * z.bytes + ((int64_t)16 << 20);
+  }
+  *bytes = std::max(*bytes, single);
+  return MCC_OK;
 }
 
 int mcc_tune_save(const mcc_tune_table* t, const char* path) {

@@ -52,7 +52,11 @@ struct BatchArgs {
   const BatchInst* inst;
   const int32_t* order;  // queue order (largest work first)
   BatchRes* res;
-  int32_t* queue;        // next queue position
+  // Queue position counter, never reset: the launch's positions start at
+  // qbase, and every workgroup takes one position past the last instance
+  // before it stops, so the next launch's base is qbase + count + grid.
+  unsigned long long* queue;
+  unsigned long long qbase;
   int32_t count;
   int32_t max_rounds;
   int32_t literal;
@@ -62,5 +66,7 @@ struct BatchArgs {
 
 bool batch_lanes_ok(int lanes);
 void launch_batch(const BatchArgs& a, int grid, hipStream_t st);
+// The persistent kernel, for a graph kernel node (one BatchArgs argument).
+const void* batch_kernel();
 
 }  // namespace mcc

@@ -830,7 +830,7 @@ void k_batch(BatchArgs b) {
   int32_t* flags = w.flags + slot * w.flag_cap;
 
   for (;;) {
-    if (t == 0) s_idx = atomicAdd(b.queue, 1);
+    if (t == 0) s_idx = (int32_t)min(atomicAdd(b.queue, 1ull) - b.qbase, (unsigned long long)b.count);
     __syncthreads();
     const int32_t qi = __builtin_amdgcn_readfirstlane(s_idx);  // uniform: scalar loads below
     __syncthreads();
@@ -899,5 +899,7 @@ bool batch_lanes_ok(int lanes) {
 void launch_batch(const BatchArgs& a, int grid, hipStream_t st) {
   k_batch<<<grid, kBlock, 0, st>>>(a);
 }
+
+const void* batch_kernel() { return reinterpret_cast<const void*>(&k_batch); }
 
 }  // namespace mcc

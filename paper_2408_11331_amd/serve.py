@@ -1,20 +1,28 @@
 """Consensus-solve serving with continuous batching on one GPU.
 
-Requests (a graph, k partitions, an optional initial consensus) arrive at
-any time.  Small requests (a few thousand vertices, where one workgroup per
-instance is the right size) are solved in batches by the persistent
-batched kernel (``mcc_consensus_batch``); larger ones by the multi-workgroup
-single-instance path (``mcc_consensus``).  Several workers, each with its
-own HIP stream, pull from one admission queue: while one batch or solve is
-on the device the next one is admitted and launched on another stream, so
-work from requests that arrived at different times overlaps on the GPU.
-Admission is bounded by an HBM budget: a request is taken only when its
-device footprint fits next to everything in flight.
+A pool of problems (a graph, k partitions, an initial consensus) is
+registered once: its arrays are uploaded and stay resident in device
+memory.  Requests name a pool entry and arrive at any time.  Worker
+threads, each with its own HIP stream, take requests from one admission
+queue: "small" workers take every small request waiting (up to max_batch)
+and solve three or more together in one persistent batched launch
+(``mcc_consensus_batch``) or fewer one by one with the multi-workgroup
+path; "large" workers solve large requests one at a time with
+``mcc_consensus``.  While one call is on the device, requests that arrive
+are admitted and launched by the other workers, so work from requests
+that arrived at different times overlaps on the GPU.
+
+Admission keeps device memory within a budget: the resident pool, the
+workspace each worker's stream keeps between calls (the library retains it
+and reports it, ``mcc_workspace_held``), and for each call in flight its
+whole workspace and outputs, counted as if none of the retained workspace
+could be reused.  A call's workspace is taken from the library's own sizing
+(``mcc_workspace_bound``, ``mcc_batch_workspace_bytes``) until a solve of
+the same entry has reported its exact figure (``workspace_bytes``).
 
 Every result is exactly the result ``mcc_consensus`` gives for the request
-alone: batching changes where a solve runs, not what it computes.
-
-This module only schedules: all computation happens in libmcc.
+alone: batching changes where a solve runs, not what it computes.  This
+module only schedules: all computation happens in libmcc.
 """
 from __future__ import annotations
 
@@ -27,12 +35,28 @@ from typing import List, Optional
 import numpy as np
 
 
+@dataclasses.dataclass(eq=False)
+class Entry:
+    """One registered problem: host arrays, their resident device copies and
+    what the admission needs to know about them."""
+    index: int
+    n: int
+    k: int
+    nnz: int
+    max_label: int
+    clusters: int          # distinct initial cluster ids (n for singletons)
+    input_bytes: int       # resident device bytes
+    bound: int             # workspace bound of one solve (library sizing)
+    measured: int = 0      # exact workspace of a finished solve, once known
+    dev: Optional[dict] = None
+
+    def workspace(self) -> int:
+        return self.measured or self.bound
+
+
 @dataclasses.dataclass(eq=False)  # requests compare by identity (queue removal)
 class Request:
-    row_ptr: np.ndarray          # int64 [n + 1]
-    col: np.ndarray              # int32 [nnz]
-    labels: np.ndarray           # int32 [k, n]
-    init: Optional[np.ndarray]   # int32 [n] or None (singletons)
+    entry: int
     rid: int = 0
     arrival: float = 0.0         # perf_counter at submission
     started: float = 0.0
@@ -42,115 +66,182 @@ class Request:
     error: Optional[str] = None
     event: threading.Event = dataclasses.field(default_factory=threading.Event)
 
-    @property
-    def n(self) -> int:
-        return int(self.row_ptr.size - 1)
 
-    @property
-    def k(self) -> int:
-        return int(self.labels.shape[0])
-
-    @property
-    def nnz(self) -> int:
-        return int(self.col.size)
-
-    def footprint(self) -> int:
-        """Device bytes held while the request is in flight: its inputs and
-        output, the vertex-major label rows, per-vertex state and a table
-        allowance."""
-        n, k, nnz = self.n, self.k, self.nnz
-        return 8 * (n + 1) + 4 * nnz + 8 * n * k + 48 * n + 16 * n * k // 4 + (1 << 16)
+def entry_from_arrays(index, row_ptr, col, labels, init):
+    """Admission figures of a problem given as host arrays (no upload)."""
+    n = int(row_ptr.size - 1)
+    k = int(labels.shape[0])
+    nnz = int(col.size)
+    max_label = int(labels.max()) if labels.size else 0
+    clusters = int(np.unique(init).size) if init is not None else n
+    input_bytes = 8 * (n + 1) + 4 * nnz + 4 * n * k + (4 * n if init is not None else 0)
+    return Entry(index, n, k, nnz, max_label, clusters, input_bytes, 0)
 
 
-def admit(queue, budget: int, in_use: int, large_n: int, want_large: bool, max_batch: int):
-    """Pick the requests one worker takes now (FIFO among the requests of
-    its kind whose footprint still fits the budget).  Pure function of its
-    arguments: returns (picked requests, bytes they hold)."""
-    picked, held = [], 0
+class Pool:
+    """Problems uploaded once and kept resident on the device."""
+
+    def __init__(self, instances, flags: int = 0, device: str = "cuda"):
+        import torch
+
+        import paper_2408_11331_amd as mcc
+        self.flags = flags
+        self.entries: List[Entry] = []
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        for j, inst in enumerate(instances):
+            e = entry_from_arrays(j, inst.row_ptr, inst.col, inst.labels, inst.init)
+            e.bound = mcc.workspace_bound(e.n, e.nnz, e.k, e.max_label, e.clusters, flags)
+            e.dev = {"row_ptr": T(inst.row_ptr), "col": T(inst.col), "labels": T(inst.labels),
+                     "init": None if inst.init is None else T(inst.init)}
+            self.entries.append(e)
+        torch.cuda.synchronize()
+        self.resident_bytes = sum(e.input_bytes for e in self.entries)
+
+    @classmethod
+    def of_entries(cls, entries: List[Entry], flags: int = 0) -> "Pool":
+        """A pool of admission figures only (nothing uploaded), for a
+        backend that does not read device arrays."""
+        p = cls.__new__(cls)
+        p.flags, p.entries = flags, list(entries)
+        p.resident_bytes = sum(e.input_bytes for e in p.entries)
+        return p
+
+    def __len__(self):
+        return len(self.entries)
+
+
+def admit(queue, entries, budget: int, in_use: int, large_n: int, want_large: bool,
+          max_batch: int, batch_ws=None):
+    """Pick the requests one worker takes now: FIFO among the requests of its
+    kind, while the call's workspace and outputs fit next to `in_use`.  A
+    request that does not fit stops the scan (later ones wait behind it).
+    Pure function of its arguments (``batch_ws(reqs)`` gives the workspace
+    of a batched call; None: the largest single solve).  Returns (requests,
+    bytes the call may add)."""
+    picked, growth = [], 0
     for r in queue:
-        if (r.n > large_n) != want_large:
+        e = entries[r.entry]
+        if (e.n > large_n) != want_large:
             continue
-        fp = r.footprint()
-        if in_use + held + fp > budget:
-            if not picked and in_use == 0 and held == 0:
-                # a request larger than the whole budget runs alone
-                picked.append(r)
-                held += fp
+        trial = picked + [r]
+        outs = sum(4 * entries[q.entry].n for q in trial)
+        if len(trial) >= 3 and batch_ws is not None:
+            ws = batch_ws(trial)
+        else:
+            ws = max(entries[q.entry].workspace() for q in trial)
+        g = ws + outs
+        if in_use + g > budget:
+            if not picked and in_use == 0:
+                picked, growth = trial, g  # larger than the whole budget: runs alone
             break
-        picked.append(r)
-        held += fp
+        picked, growth = trial, g
         if want_large or len(picked) >= max_batch:
             break
-    return picked, held
+    return picked, growth
 
 
 class GpuBackend:
-    """Solves admitted requests with libmcc on the worker's own HIP stream."""
+    """Solves admitted requests with libmcc on the worker's own HIP stream,
+    from the pool's resident arrays."""
 
-    def __init__(self, max_rounds: int = 0):
+    def __init__(self, pool: Pool, max_rounds: int = 0):
         import torch
+
         import paper_2408_11331_amd as mcc
         mcc.lib()
-        self.torch, self.mcc, self.max_rounds = torch, mcc, max_rounds
+        self.torch, self.mcc, self.pool, self.max_rounds = torch, mcc, pool, max_rounds
 
     def make_stream(self):
         return self.torch.cuda.Stream()  # default priority
 
-    def _upload(self, r: Request):
-        T = lambda a: self.torch.from_numpy(np.ascontiguousarray(a)).cuda()
-        return {"row_ptr": T(r.row_ptr), "col": T(r.col), "labels": T(r.labels),
-                "init": None if r.init is None else T(r.init)}
+    def held(self, stream) -> int:
+        return self.mcc.workspace_held(stream)
 
-    def solve(self, reqs: List[Request], large: bool, stream) -> None:
+    def batch_ws(self, reqs: List[Request]) -> int:
+        return self.mcc.batch_workspace_bytes([self.pool.entries[r.entry].dev for r in reqs])
+
+    def solve(self, reqs: List[Request], stream) -> None:
+        """Solve, fill each request's out and stats."""
         torch, mcc = self.torch, self.mcc
+        entries = self.pool.entries
         with torch.cuda.stream(stream):
-            if large:
-                for r in reqs:
-                    d = self._upload(r)
-                    out, st = mcc.consensus(d["row_ptr"], d["col"], d["labels"], d["init"],
-                                            max_rounds=self.max_rounds, stream=stream)
-                    r.out, r.stats = out.cpu().numpy(), st
-            else:
-                # the batch's requests concatenated in one upload
-                pb = mcc.pack_batch(reqs)
-                mcc.consensus_batch_packed(pb, max_rounds=self.max_rounds, stream=stream)
-                out = pb.out.cpu().numpy()
-                for j, r in enumerate(reqs):
-                    c = pb.status[j]
-                    if c != 0:
-                        r.error = mcc.lib().mcc_strerror(c).decode()
-                    o = int(pb.v_off[j])
-                    r.out, r.stats = out[o:o + r.n], pb.stats[j].as_dict()
-            stream.synchronize()
+            outs = [torch.empty(entries[r.entry].n, dtype=torch.int32, device="cuda")
+                    for r in reqs]
+        if len(reqs) >= 3:
+            probs = [entries[r.entry].dev for r in reqs]
+            _, stats, codes, info = mcc.consensus_batch(probs, max_rounds=self.max_rounds,
+                                                        flags=self.pool.flags, stream=stream,
+                                                        outs=outs)
+            for r, c, st in zip(reqs, codes, stats):
+                if c != 0:
+                    r.error = mcc.lib().mcc_strerror(c).decode()
+                r.stats = st
+        else:
+            for r, o in zip(reqs, outs):
+                d = entries[r.entry].dev
+                _, st = mcc.consensus(d["row_ptr"], d["col"], d["labels"], d["init"],
+                                      max_rounds=self.max_rounds, flags=self.pool.flags,
+                                      stream=stream, out=o)
+                r.stats = st
+                e = entries[r.entry]
+                e.measured = max(e.measured, st["workspace_bytes"])
+        with torch.cuda.stream(stream):
+            host = [o.cpu() for o in outs]  # synchronous copies on the worker's stream
+        for r, h in zip(reqs, host):
+            r.out = h.numpy()
 
 
 class Server:
-    """Admission queue plus worker threads that own one stream each."""
+    """Admission queue plus worker threads that own one stream each.
 
-    def __init__(self, budget_bytes: int = 16 << 30, large_n: int = 8192,
+    Each worker first warms its stream up (one solve of the smallest entry
+    of its kind, and for small workers one batched call, which sets up the
+    batched launch's graph), so that the first requests pay no set-up; the
+    constructor returns once every worker is ready."""
+
+    def __init__(self, pool: Pool, budget_bytes: int = 64 << 30, large_n: int = 50_000,
                  max_batch: int = 256, small_workers: int = 2, large_workers: int = 3,
-                 max_rounds: int = 0, backend=None):
-        self.backend = backend if backend is not None else GpuBackend(max_rounds)
+                 max_rounds: int = 0, backend=None, warm: bool = True):
+        self.pool = pool
+        self.backend = backend if backend is not None else GpuBackend(pool, max_rounds)
         self.budget = int(budget_bytes)
+        if pool.resident_bytes > self.budget:
+            raise ValueError("the resident pool alone exceeds the budget")
         self.large_n = int(large_n)
         self.max_batch = int(max_batch)
         self.queue = collections.deque()
         self.cv = threading.Condition()
-        self.in_use = 0
         self.running = True
         self.completed: List[Request] = []
+        self.retained = {}      # worker -> workspace its stream keeps (library figure)
+        self.growth = {}        # worker -> bytes its call in flight may add
         self.peak_in_use = 0
         self.batches = 0
         self.threads = []
-        for j in range(small_workers):
-            self.threads.append(threading.Thread(target=self._worker, args=(False,), daemon=True))
-        for j in range(large_workers):
-            self.threads.append(threading.Thread(target=self._worker, args=(True,), daemon=True))
+        kinds = [False] * small_workers + [True] * large_workers
+        ready = threading.Barrier(len(kinds) + 1)
+        for w, large in enumerate(kinds):
+            self.retained[w] = 0
+            self.growth[w] = 0
+            self.threads.append(threading.Thread(target=self._worker, args=(w, large, warm, ready),
+                                                 daemon=True))
+        self.warm_errors: List[str] = []
         for t in self.threads:
             t.start()
+        ready.wait()
+        if self.warm_errors:
+            self.close()
+            raise RuntimeError("worker warm-up failed: " + "; ".join(self.warm_errors))
+
+    def in_use(self) -> int:
+        """Bytes accounted for: resident pool, retained workspaces, calls in
+        flight (caller holds the lock)."""
+        return (self.pool.resident_bytes + sum(self.retained.values()) +
+                sum(self.growth.values()))
 
     # -- client side ----------------------------------------------------------
-    def submit(self, req: Request) -> Request:
+    def submit(self, entry: int, rid: int = 0) -> Request:
+        req = Request(entry, rid=rid)
         req.arrival = time.perf_counter()
         with self.cv:
             self.queue.append(req)
@@ -165,35 +256,64 @@ class Server:
             t.join()
 
     # -- workers ----------------------------------------------------------------
-    def _worker(self, large: bool):
+    def _warm(self, w: int, large: bool, stream):
+        entries = self.pool.entries
+        mine = [e for e in entries if (e.n > self.large_n) == large]
+        if not mine:
+            return
+        e = min(mine, key=lambda x: x.n)
+        calls = [[Request(e.index)]]
+        if not large:
+            calls.append([Request(e.index) for _ in range(3)])
+        for reqs in calls:
+            self.backend.solve(reqs, stream)
+        with self.cv:
+            self.retained[w] = self.backend.held(stream)
+
+    def _worker(self, w: int, large: bool, warm: bool, ready):
         stream = self.backend.make_stream()
+        entries = self.pool.entries
+        bws = None if large else self.backend.batch_ws
+        try:
+            if warm:
+                self._warm(w, large, stream)
+        except Exception as e:
+            with self.cv:
+                self.warm_errors.append(f"worker {w}: {type(e).__name__}: {e}")
+            ready.wait()
+            return
+        ready.wait()
         while True:
             with self.cv:
                 while True:
-                    picked, held = admit(self.queue, self.budget, self.in_use, self.large_n,
-                                         large, self.max_batch)
+                    picked, growth = admit(self.queue, entries, self.budget, self.in_use(),
+                                           self.large_n, large, self.max_batch, bws)
                     if picked:
                         break
-                    mine = any((r.n > self.large_n) == large for r in self.queue)
+                    mine = any((entries[r.entry].n > self.large_n) == large for r in self.queue)
                     if not self.running and not mine:
                         return
-                    self.cv.wait(timeout=0.05)
+                    self.cv.wait()
                 for r in picked:
                     self.queue.remove(r)
-                self.in_use += held
-                self.peak_in_use = max(self.peak_in_use, self.in_use)
+                self.growth[w] = growth
+                self.peak_in_use = max(self.peak_in_use, self.in_use())
                 self.batches += 1
             t0 = time.perf_counter()
             for r in picked:
                 r.started = t0
+            held = None
             try:
-                self.backend.solve(picked, large, stream)
+                self.backend.solve(picked, stream)
+                held = self.backend.held(stream)
             except Exception as e:  # reported per request, the server keeps going
                 for r in picked:
                     r.error = f"{type(e).__name__}: {e}"
             t1 = time.perf_counter()
             with self.cv:
-                self.in_use -= held
+                self.growth[w] = 0
+                if held is not None:
+                    self.retained[w] = held
                 for r in picked:
                     r.done_at = t1
                     self.completed.append(r)
@@ -215,54 +335,64 @@ def poisson_arrivals(rate: float, count: int, seed: int) -> np.ndarray:
     return np.cumsum(rng.exponential(1.0 / rate, size=count))
 
 
-def run_served(pool: List[Request], rate: float, count: int, seed: int = 0, wait_s: float = 600.0,
-               **server_kw):
-    """Replay `count` requests drawn from `pool` with Poisson arrivals at
-    `rate` per second through a Server; returns (requests, summary)."""
+def request_stream(weights, rate: float, count: int, seed: int):
+    """Entries (drawn with the given weights) and arrival offsets (s)."""
     rng = np.random.Generator(np.random.PCG64(seed + 1))
-    picks = rng.integers(0, len(pool), size=count)
-    times = poisson_arrivals(rate, count, seed)
-    srv = Server(**server_kw)
+    p = np.asarray(weights, np.float64)
+    picks = rng.choice(len(p), size=count, p=p / p.sum())
+    return picks, poisson_arrivals(rate, count, seed)
+
+
+def run_served(pool: Pool, weights, rate: float, count: int, seed: int = 0,
+               wait_s: float = 600.0, **server_kw):
+    """Replay `count` requests with Poisson arrivals at `rate` per second
+    through a Server; returns (requests, summary)."""
+    picks, times = request_stream(weights, rate, count, seed)
+    srv = Server(pool, **server_kw)
     reqs = []
     t0 = time.perf_counter()
-    for j, (p, at) in enumerate(zip(picks, times)):
+    for p, at in zip(picks, times):
         delay = t0 + at - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
-        src = pool[p]
-        reqs.append(srv.submit(Request(src.row_ptr, src.col, src.labels, src.init, rid=int(p))))
+        reqs.append(srv.submit(int(p), rid=int(p)))
     deadline = time.perf_counter() + wait_s
     for r in reqs:
         if not r.event.wait(max(0.0, deadline - time.perf_counter())):
-            raise TimeoutError(f"request {r.rid} not served within {wait_s} s")
+            raise TimeoutError(f"request for entry {r.entry} not served within {wait_s} s")
     srv.close()
     summ = latency_summary(reqs)
-    summ.update(batches=srv.batches, peak_in_use_bytes=srv.peak_in_use)
+    summ.update(batches=srv.batches, peak_accounted_bytes=srv.peak_in_use,
+                retained_bytes=sum(srv.retained.values()), budget_bytes=srv.budget,
+                resident_bytes=pool.resident_bytes)
     return reqs, summ
 
 
-def run_one_at_a_time(pool: List[Request], rate: float, count: int, seed: int = 0,
+def run_one_at_a_time(pool: Pool, weights, rate: float, count: int, seed: int = 0,
                       max_rounds: int = 0):
-    """The plain path on the same arrivals: one solve at a time, in arrival
-    order, with mcc_consensus on one stream."""
+    """The plain path on the same arrivals: one mcc_consensus at a time, in
+    arrival order, on one stream, from the same resident arrays."""
     import torch
+
     import paper_2408_11331_amd as mcc
-    rng = np.random.Generator(np.random.PCG64(seed + 1))
-    picks = rng.integers(0, len(pool), size=count)
-    times = poisson_arrivals(rate, count, seed)
-    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    picks, times = request_stream(weights, rate, count, seed)
+    small = min(pool.entries, key=lambda x: x.n).dev
+    mcc.consensus(small["row_ptr"], small["col"], small["labels"], small["init"],
+                  max_rounds=max_rounds, flags=pool.flags)  # warm-up, as the server's workers
     reqs = []
     t0 = time.perf_counter()
     for p, at in zip(picks, times):
         now = time.perf_counter()
         if now < t0 + at:
             time.sleep(t0 + at - now)
-        src = pool[p]
-        r = Request(src.row_ptr, src.col, src.labels, src.init, rid=int(p))
+        e = pool.entries[int(p)]
+        r = Request(int(p), rid=int(p))
         r.arrival = t0 + at
-        out, st = mcc.consensus(T(r.row_ptr), T(r.col), T(r.labels),
-                                None if r.init is None else T(r.init), max_rounds=max_rounds)
+        d = e.dev
+        out, st = mcc.consensus(d["row_ptr"], d["col"], d["labels"], d["init"],
+                                max_rounds=max_rounds, flags=pool.flags)
         r.out, r.stats = out.cpu().numpy(), st
         r.done_at = time.perf_counter()
         reqs.append(r)
+    torch.cuda.synchronize()
     return reqs, latency_summary(reqs)
