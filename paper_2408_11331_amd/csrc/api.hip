@@ -336,6 +336,20 @@ struct Solve {
 // Largest cluster count for which labels are aligned to clusters.
 constexpr int32_t kAlignMaxClusters = 1 << 16;
 
+// Largest dense table (cells) a solve may choose.  Dense tables are kept
+// while they stay within 16 n k cells (or 2^24); with clusters few enough
+// to align, up to 2^30 cells (4 GiB of blocked counts): the aligned
+// interleaved layout puts the counts a vertex reads for one candidate in
+// one or two lines however large the table is, where a hashed table spreads
+// them over k lines.
+constexpr int64_t kDenseAlignedMax = (int64_t)1 << 30;
+
+int64_t dense_cells_max(int64_t n, int32_t k, int64_t K0, bool want_rows) {
+  int64_t lim = std::max<int64_t>((int64_t)1 << 24, 16 * n * (int64_t)k);
+  if (want_rows && K0 <= kAlignMaxClusters) lim = std::max(lim, kDenseAlignedMax);
+  return std::min(lim, kMaxTableEntries);
+}
+
 // Blocked tables for the current label ids: allocation, zero fill, build.
 Tables blocked_tables(Arena& ar, const Solve& S, const int32_t* Ldev,
                       const std::vector<int32_t>& Lh, hipStream_t st, int64_t* total) {
@@ -454,10 +468,10 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
     sumL += Lh[i];
   }
   // Hashed tables when the dense ones would not fit, or would be far larger
-  // than the n k keys a hashed table holds at most.
+  // than the n k keys a hashed table holds at most (unless they can be
+  // aligned: dense_cells_max).
   const int64_t dense = (int64_t)K0 * sumL;
-  if (force_hash || dense > kMaxTableEntries ||
-      (dense > ((int64_t)1 << 24) && dense > 16 * n * (int64_t)k)) {
+  if (force_hash || dense > dense_cells_max(n, k, K0, want_rows)) {
     int bits = 12;
     while (((int64_t)1 << bits) < 4 * n * (int64_t)k) ++bits;
     const int64_t slots = (int64_t)1 << bits;
@@ -528,7 +542,8 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
     int32_t Lmax = 1;
     for (int i = 0; i < k; ++i) Lmax = std::max(Lmax, L2h[i]);
     const int64_t cells = (int64_t)K0 * Lmax * k;
-    if (cells <= kMaxTableEntries && cells <= 2 * total + ((int64_t)1 << 20)) {
+    if (cells <= kMaxTableEntries && cells <= 2 * total + ((int64_t)1 << 20) &&
+        cells + 2 * (int64_t)K0 < ((int64_t)1 << 31)) {
       launch_fmap_update(S->lab.scan, S->lab.loff, dpoff, amap, k, S->lab.max_span,
                          S->lab.fmap, st);
       Tables it{};
@@ -1823,7 +1838,7 @@ int mcc_workspace_bound(int64_t n, int64_t nnz, int32_t k, int64_t max_label, in
   add(4 * n); add(4 * K0); add(4 * K0);
   // tables: the dense layouts (blocked, alignment, interleaved) when they
   // can be chosen, the hashed table when it can
-  const int64_t dense_cap = std::max<int64_t>((int64_t)1 << 24, 16 * nk);
+  const int64_t dense_cap = dense_cells_max(n, k, K0, true);
   const int64_t dense_ub = K0 * sumL;  // clusters x labels, at most
   const bool can_hash = dense_ub > std::min<int64_t>(kMaxTableEntries, dense_cap);
   const int64_t dense = std::min<int64_t>(dense_ub, std::min<int64_t>(kMaxTableEntries, dense_cap));
@@ -1832,7 +1847,7 @@ int mcc_workspace_bound(int64_t n, int64_t nnz, int32_t k, int64_t max_label, in
     std::swap(small, dsmall);
     std::swap(big, dbig);
     add(8 * (k + 1)); add(4 * dense);
-    if (K0 <= (1 << 16)) {
+    if (K0 <= kAlignMaxClusters) {
       add(8 * k * K0);
       for (int j = 0; j < 3; ++j) add(4 * (sumL + 1));
       add(8 * sumL); add(4 * sumL); add(4 * (scan_tmp_elems(sumL) + 1)); add(4 * k);

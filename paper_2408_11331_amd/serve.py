@@ -2,15 +2,18 @@
 
 A pool of problems (a graph, k partitions, an initial consensus) is
 registered once: its arrays are uploaded and stay resident in device
-memory.  Requests name a pool entry and arrive at any time.  Worker
-threads, each with its own HIP stream, take requests from one admission
-queue: "small" workers take every small request waiting (up to max_batch)
-and solve three or more together in one persistent batched launch
-(``mcc_consensus_batch``) or fewer one by one with the multi-workgroup
-path; "large" workers solve large requests one at a time with
-``mcc_consensus``.  While one call is on the device, requests that arrive
-are admitted and launched by the other workers, so work from requests
-that arrived at different times overlaps on the GPU.
+memory, and each entry is timed once on the multi-workgroup path
+(``mcc_consensus``) and, if it is small enough, alone in the persistent
+batched launch (``mcc_consensus_batch``, one workgroup per instance).
+Requests name a pool entry and arrive at any time.  Worker threads, each
+with its own HIP stream, take requests from one admission queue in arrival
+order: "small" workers take the oldest small request and, when it pays,
+the other waiting small requests with it in one batched launch — a batched
+call lasts about as long as its slowest instance, so requests join the
+call while that stays below the time solving them one by one would take;
+otherwise the request is solved alone.  "Large" workers solve large
+requests one at a time.  Calls on different workers' streams overlap on the
+GPU, so requests that arrive while others are being solved start at once.
 
 Admission keeps device memory within a budget: the resident pool, the
 workspace each worker's stream keeps between calls (the library retains it
@@ -49,6 +52,8 @@ class Entry:
     bound: int             # workspace bound of one solve (library sizing)
     measured: int = 0      # exact workspace of a finished solve, once known
     dev: Optional[dict] = None
+    t_single: Optional[float] = None  # seconds, alone on the multi-workgroup path
+    t_batch: Optional[float] = None   # seconds, alone in a batched launch (None: never batched)
 
     def workspace(self) -> int:
         return self.measured or self.bound
@@ -81,7 +86,8 @@ def entry_from_arrays(index, row_ptr, col, labels, init):
 class Pool:
     """Problems uploaded once and kept resident on the device."""
 
-    def __init__(self, instances, flags: int = 0, device: str = "cuda"):
+    def __init__(self, instances, flags: int = 0, device: str = "cuda", calibrate: bool = True,
+                 batch_n_max: int = 16384, batch_ratio_max: float = 4.0):
         import torch
 
         import paper_2408_11331_amd as mcc
@@ -96,6 +102,43 @@ class Pool:
             self.entries.append(e)
         torch.cuda.synchronize()
         self.resident_bytes = sum(e.input_bytes for e in self.entries)
+        if calibrate:
+            self.calibrate(batch_n_max, batch_ratio_max)
+
+    def calibrate(self, batch_n_max: int = 16384, batch_ratio_max: float = 4.0,
+                  max_rounds: int = 0):
+        """Time every entry alone on the multi-workgroup path and, if it has
+        at most batch_n_max vertices and 256 partitions, two copies of it in
+        one batched launch (after one untimed call of each that sets the
+        path up).  An entry is batched only if two copies take no longer
+        than 1.5 times one copy (else the launch hands it back to the
+        multi-workgroup path one copy after the other) and at most
+        batch_ratio_max times its time alone."""
+        import torch
+
+        import paper_2408_11331_amd as mcc
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            return time.perf_counter() - t
+
+        for e in self.entries:
+            d = e.dev
+            e.t_single = timed(lambda: mcc.consensus(d["row_ptr"], d["col"], d["labels"],
+                                                     d["init"], max_rounds=max_rounds,
+                                                     flags=self.flags))
+            e.t_batch = None
+            if e.n <= batch_n_max and e.k <= 256:
+                t1 = timed(lambda: mcc.consensus_batch([d], max_rounds=max_rounds,
+                                                       flags=self.flags))
+                t2 = timed(lambda: mcc.consensus_batch([d, d], max_rounds=max_rounds,
+                                                       flags=self.flags))
+                if t2 <= 1.5 * t1 and t2 <= batch_ratio_max * e.t_single:
+                    e.t_batch = t2
 
     @classmethod
     def of_entries(cls, entries: List[Entry], flags: int = 0) -> "Pool":
@@ -110,34 +153,68 @@ class Pool:
         return len(self.entries)
 
 
-def admit(queue, entries, budget: int, in_use: int, large_n: int, want_large: bool,
-          max_batch: int, batch_ws=None):
-    """Pick the requests one worker takes now: FIFO among the requests of its
-    kind, while the call's workspace and outputs fit next to `in_use`.  A
-    request that does not fit stops the scan (later ones wait behind it).
-    Pure function of its arguments (``batch_ws(reqs)`` gives the workspace
-    of a batched call; None: the largest single solve).  Returns (requests,
-    bytes the call may add)."""
-    picked, growth = [], 0
-    for r in queue:
+def choose_batch(mine, entries, max_batch: int, workers: int = 1):
+    """The requests to solve with the oldest one, mine[0], in one batched
+    call, or [] if it should be solved alone.  A batched call lasts about as
+    long as its slowest instance and holds one of `workers` workers that
+    would otherwise share the requests: among the waiting requests that may
+    be batched, taken in increasing batched time, the longest run that
+    includes mine[0] and whose slowest batched time stays within the sum of
+    their times alone divided by `workers`."""
+    head = mine[0]
+    if entries[head.entry].t_batch is None:
+        return []
+    cand = sorted((r for r in mine if entries[r.entry].t_batch is not None),
+                  key=lambda r: entries[r.entry].t_batch)[:max_batch]
+    if head not in cand:  # more than max_batch requests are cheaper than the head
+        cand = cand[:max_batch - 1] + [head]
+        cand.sort(key=lambda r: entries[r.entry].t_batch)
+    best, alone, has_head = [], 0.0, False
+    for m, r in enumerate(cand, 1):
         e = entries[r.entry]
-        if (e.n > large_n) != want_large:
-            continue
-        trial = picked + [r]
-        outs = sum(4 * entries[q.entry].n for q in trial)
-        if len(trial) >= 3 and batch_ws is not None:
-            ws = batch_ws(trial)
-        else:
-            ws = max(entries[q.entry].workspace() for q in trial)
-        g = ws + outs
-        if in_use + g > budget:
-            if not picked and in_use == 0:
-                picked, growth = trial, g  # larger than the whole budget: runs alone
-            break
-        picked, growth = trial, g
-        if want_large or len(picked) >= max_batch:
-            break
-    return picked, growth
+        alone += e.t_single
+        has_head = has_head or r is head
+        if has_head and m >= 2 and e.t_batch * workers <= alone:
+            best = cand[:m]
+    return best
+
+
+def admit(queue, entries, budget: int, in_use: int, retained: int, large_n: int,
+          want_large: bool, max_batch: int, batch_ws=None, idle: bool = False,
+          before: float = float("inf"), workers: int = 1):
+    """Pick the call one worker (of `workers` of its kind) makes now: the
+    oldest request of its kind that arrived before `before`, with the
+    requests ``choose_batch`` joins to it when the worker batches (``batch_ws(reqs)`` gives the workspace
+    of a batched call; None: never batch).  The call's workspace and outputs
+    must fit next to `in_use` (of which `retained` is idle workspace the
+    library keeps): a batch that does not fit shrinks to the oldest request
+    alone, and a request that does not fit alone waits (requests behind it
+    wait too), unless no call is in flight (`idle`): then it is taken alone,
+    after the retained workspace is released if there is any (`reclaim`) —
+    also when it needs more than the whole budget.  Pure function of its
+    arguments.  Returns (requests, bytes the call may add, reclaim,
+    batched)."""
+    mine = []
+    for r in queue:
+        if r.arrival >= before:
+            break  # the queue is in arrival order
+        if (entries[r.entry].n > large_n) == want_large:
+            mine.append(r)
+    if not mine:
+        return [], 0, False, False
+    head = mine[0]
+    g1 = entries[head.entry].workspace() + 4 * entries[head.entry].n
+    if in_use + g1 > budget:
+        if idle:
+            return [head], g1, retained > 0, False
+        return [], 0, False, False
+    if not want_large and batch_ws is not None and max_batch > 1:
+        group = choose_batch(mine, entries, max_batch, workers)
+        if group:
+            g = batch_ws(group) + sum(4 * entries[r.entry].n for r in group)
+            if in_use + g <= budget:
+                return group, g, False, True
+    return [head], g1, False, False
 
 
 class GpuBackend:
@@ -157,17 +234,22 @@ class GpuBackend:
     def held(self, stream) -> int:
         return self.mcc.workspace_held(stream)
 
+    def release(self) -> None:
+        """Free the library's idle workspace (no call may be in flight)."""
+        self.mcc.release_workspace()
+
     def batch_ws(self, reqs: List[Request]) -> int:
         return self.mcc.batch_workspace_bytes([self.pool.entries[r.entry].dev for r in reqs])
 
-    def solve(self, reqs: List[Request], stream) -> None:
-        """Solve, fill each request's out and stats."""
+    def solve(self, reqs: List[Request], stream, batched: bool = False) -> None:
+        """Solve (in one batched call, or one by one), fill each request's
+        out and stats."""
         torch, mcc = self.torch, self.mcc
         entries = self.pool.entries
         with torch.cuda.stream(stream):
             outs = [torch.empty(entries[r.entry].n, dtype=torch.int32, device="cuda")
                     for r in reqs]
-        if len(reqs) >= 3:
+        if batched:
             probs = [entries[r.entry].dev for r in reqs]
             _, stats, codes, info = mcc.consensus_batch(probs, max_rounds=self.max_rounds,
                                                         flags=self.pool.flags, stream=stream,
@@ -200,7 +282,7 @@ class Server:
     constructor returns once every worker is ready."""
 
     def __init__(self, pool: Pool, budget_bytes: int = 64 << 30, large_n: int = 50_000,
-                 max_batch: int = 256, small_workers: int = 2, large_workers: int = 3,
+                 max_batch: int = 512, small_workers: int = 4, large_workers: int = 2,
                  max_rounds: int = 0, backend=None, warm: bool = True):
         self.pool = pool
         self.backend = backend if backend is not None else GpuBackend(pool, max_rounds)
@@ -215,14 +297,19 @@ class Server:
         self.completed: List[Request] = []
         self.retained = {}      # worker -> workspace its stream keeps (library figure)
         self.growth = {}        # worker -> bytes its call in flight may add
+        self.blocked = {}       # worker -> arrival of its request waiting for memory
         self.peak_in_use = 0
-        self.batches = 0
+        self.batches = 0        # calls made
+        self.batched_calls = 0  # of which batched launches
+        self.reclaims = 0
         self.threads = []
         kinds = [False] * small_workers + [True] * large_workers
+        self.kinds = kinds
         ready = threading.Barrier(len(kinds) + 1)
         for w, large in enumerate(kinds):
             self.retained[w] = 0
             self.growth[w] = 0
+            self.blocked[w] = None
             self.threads.append(threading.Thread(target=self._worker, args=(w, large, warm, ready),
                                                  daemon=True))
         self.warm_errors: List[str] = []
@@ -262,11 +349,9 @@ class Server:
         if not mine:
             return
         e = min(mine, key=lambda x: x.n)
-        calls = [[Request(e.index)]]
-        if not large:
-            calls.append([Request(e.index) for _ in range(3)])
-        for reqs in calls:
-            self.backend.solve(reqs, stream)
+        self.backend.solve([Request(e.index)], stream)
+        if not large and e.t_batch is not None:
+            self.backend.solve([Request(e.index) for _ in range(3)], stream, batched=True)
         with self.cv:
             self.retained[w] = self.backend.held(stream)
 
@@ -283,28 +368,47 @@ class Server:
             ready.wait()
             return
         ready.wait()
+        inf = float("inf")
         while True:
             with self.cv:
                 while True:
-                    picked, growth = admit(self.queue, entries, self.budget, self.in_use(),
-                                           self.large_n, large, self.max_batch, bws)
+                    # a request another worker holds back for memory goes first:
+                    # take nothing that arrived after it
+                    before = min((t for v, t in self.blocked.items()
+                                  if v != w and t is not None), default=inf)
+                    idle = not any(self.growth.values())
+                    picked, growth, reclaim, batched = admit(
+                        self.queue, entries, self.budget, self.in_use(),
+                        sum(self.retained.values()), self.large_n, large, self.max_batch, bws,
+                        idle=idle, before=before,
+                        workers=self.kinds.count(large))
                     if picked:
+                        self.blocked[w] = None
+                        if reclaim:
+                            self.backend.release()
+                            for v in self.retained:
+                                self.retained[v] = 0
+                            self.reclaims += 1
                         break
-                    mine = any((entries[r.entry].n > self.large_n) == large for r in self.queue)
-                    if not self.running and not mine:
+                    head = next((r for r in self.queue
+                                 if (entries[r.entry].n > self.large_n) == large), None)
+                    if not self.running and head is None:
                         return
+                    self.blocked[w] = head.arrival if head is not None and \
+                        head.arrival < before else None
                     self.cv.wait()
                 for r in picked:
                     self.queue.remove(r)
                 self.growth[w] = growth
                 self.peak_in_use = max(self.peak_in_use, self.in_use())
                 self.batches += 1
+                self.batched_calls += 1 if batched else 0
             t0 = time.perf_counter()
             for r in picked:
                 r.started = t0
             held = None
             try:
-                self.backend.solve(picked, stream)
+                self.backend.solve(picked, stream, batched)
                 held = self.backend.held(stream)
             except Exception as e:  # reported per request, the server keeps going
                 for r in picked:
@@ -362,7 +466,7 @@ def run_served(pool: Pool, weights, rate: float, count: int, seed: int = 0,
             raise TimeoutError(f"request for entry {r.entry} not served within {wait_s} s")
     srv.close()
     summ = latency_summary(reqs)
-    summ.update(batches=srv.batches, peak_accounted_bytes=srv.peak_in_use,
+    summ.update(batches=srv.batches, batched_calls=srv.batched_calls, reclaims=srv.reclaims, peak_accounted_bytes=srv.peak_in_use,
                 retained_bytes=sum(srv.retained.values()), budget_bytes=srv.budget,
                 resident_bytes=pool.resident_bytes)
     return reqs, summ
