@@ -337,16 +337,19 @@ struct Solve {
 constexpr int32_t kAlignMaxClusters = 1 << 16;
 
 // Largest dense table (cells) a solve may choose.  Dense tables are kept
-// while they stay within 16 n k cells (or 2^24); with clusters few enough
-// to align, up to 2^30 cells (4 GiB of blocked counts): the aligned
-// interleaved layout puts the counts a vertex reads for one candidate in
-// one or two lines however large the table is, where a hashed table spreads
-// them over k lines.
+// while they stay within 16 n k cells (or 2^24); when the clusters can be
+// aligned with the labels, up to 2^30 cells (4 GiB of blocked counts): the
+// aligned interleaved layout puts the counts a vertex reads for one
+// candidate in one or two lines however large the table is, where a hashed
+// table spreads them over k lines.  Alignment gives every partition at
+// least K0 label ids, and its table is kept only within about twice the
+// blocked one, so it needs K0 k <= 2 sum_i L_i (not so from singletons).
 constexpr int64_t kDenseAlignedMax = (int64_t)1 << 30;
 
-int64_t dense_cells_max(int64_t n, int32_t k, int64_t K0, bool want_rows) {
+int64_t dense_cells_max(int64_t n, int32_t k, int64_t K0, int64_t sumL, bool want_rows) {
   int64_t lim = std::max<int64_t>((int64_t)1 << 24, 16 * n * (int64_t)k);
-  if (want_rows && K0 <= kAlignMaxClusters) lim = std::max(lim, kDenseAlignedMax);
+  if (want_rows && K0 <= kAlignMaxClusters && K0 * k <= 2 * sumL)
+    lim = std::max(lim, kDenseAlignedMax);
   return std::min(lim, kMaxTableEntries);
 }
 
@@ -471,7 +474,7 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
   // than the n k keys a hashed table holds at most (unless they can be
   // aligned: dense_cells_max).
   const int64_t dense = (int64_t)K0 * sumL;
-  if (force_hash || dense > dense_cells_max(n, k, K0, want_rows)) {
+  if (force_hash || dense > dense_cells_max(n, k, K0, sumL, want_rows)) {
     int bits = 12;
     while (((int64_t)1 << bits) < 4 * n * (int64_t)k) ++bits;
     const int64_t slots = (int64_t)1 << bits;
@@ -505,7 +508,7 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
     launch_fill_u64(reinterpret_cast<uint64_t*>(S->acc), 3, 0ull, st);
     int32_t* hist = ar.get<int32_t>(sumL);
     launch_objective0_hashed(t, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, S->s, sumL,
-                             hist, S->acc, st);
+                             hist, init == nullptr, S->acc, st);
     return;
   }
   // Blocked tables with dense label ids: the final tables when the labels
@@ -521,6 +524,7 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
   S->maxL = maxL;
   S->total = total;
   bool aligned = false;
+  std::vector<int32_t> Lfinal = Lh;  // label ids per partition in the final layout
 
   if (try_align) {
     std::vector<int64_t> poff(k + 1, 0);
@@ -559,6 +563,7 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
       S->maxL = Lmax;
       S->total = cells;
       aligned = true;
+      Lfinal = L2h;
     }
   }
   if (try_align && !aligned && stride > 1) {  // sampled blocked tables: count them all
@@ -571,7 +576,18 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
   }
   S->acc = ar.get<int64_t>(3);
   launch_fill_u64(reinterpret_cast<uint64_t*>(S->acc), 3, 0ull, st);
-  launch_objective0(S->t, k, K0, S->maxL, S->s, S->total, S->acc, st);
+  std::vector<int64_t> lpoff(k + 1, 0);
+  for (int i = 0; i < k; ++i) lpoff[i + 1] = lpoff[i] + Lfinal[i];
+  LabelHist lh{};
+  lh.dlabels = S->lab.dlabels;
+  lh.loff = S->lab.loff;
+  lh.fmap = S->lab.fmap;
+  int64_t* dlpoff = ar.get<int64_t>(k + 1);
+  h2d(dlpoff, ar.host(lpoff), k + 1, st);
+  lh.lpoff = dlpoff;
+  lh.total_labels = lpoff[k];
+  lh.hist = ar.get<int32_t>(lpoff[k]);
+  launch_objective0(S->t, k, K0, S->s, S->total, lh, S->C, S->Lvm, n, S->acc, st);
 }
 
 int translate(const std::exception_ptr& ep) {
@@ -1838,7 +1854,7 @@ int mcc_workspace_bound(int64_t n, int64_t nnz, int32_t k, int64_t max_label, in
   add(4 * n); add(4 * K0); add(4 * K0);
   // tables: the dense layouts (blocked, alignment, interleaved) when they
   // can be chosen, the hashed table when it can
-  const int64_t dense_cap = dense_cells_max(n, k, K0, true);
+  const int64_t dense_cap = dense_cells_max(n, k, K0, sumL, true);
   const int64_t dense_ub = K0 * sumL;  // clusters x labels, at most
   const bool can_hash = dense_ub > std::min<int64_t>(kMaxTableEntries, dense_cap);
   const int64_t dense = std::min<int64_t>(dense_ub, std::min<int64_t>(kMaxTableEntries, dense_cap));
@@ -1847,6 +1863,7 @@ int mcc_workspace_bound(int64_t n, int64_t nnz, int32_t k, int64_t max_label, in
     std::swap(small, dsmall);
     std::swap(big, dbig);
     add(8 * (k + 1)); add(4 * dense);
+    add(8 * (k + 1)); add(4 * ((int64_t)k * K0 + sumL));  // label sizes
     if (K0 <= kAlignMaxClusters) {
       add(8 * k * K0);
       for (int j = 0; j < 3; ++j) add(4 * (sumL + 1));

@@ -194,17 +194,34 @@ void launch_build(const int32_t* C, const int32_t* const* dlabels, const int64_t
                   const int32_t* fmap, int64_t n, int32_t k, int32_t K0, int32_t max_l, Tables t,
                   hipStream_t st, int64_t stride = 1);
 void launch_sizes(const int32_t* C, int64_t n, int32_t K0, int32_t* s, hipStream_t st);
-void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, const int32_t* s,
-                       int64_t total_entries,
+// Label sizes |P_i l| counted from the labels: the ids label l of
+// partition i has in some layout (labels[i][v] through fmap + loff[i]) lie
+// in [0, lpoff[i + 1] - lpoff[i]); hist (lpoff[k] entries) is scratch.
+struct LabelHist {
+  const int32_t* const* dlabels;
+  const int64_t* loff;
+  const int32_t* fmap;
+  const int64_t* lpoff;
+  int64_t total_labels;
+  int32_t* hist;
+};
+// acc[0] += sum_x s_x^2; acc[1] += sum_i sum_l |P_i l|^2 (from the label
+// histogram); acc[2] += sum over cells of N^2: a scan of the `total_entries`
+// cells, or, when the label rows Lvm are given and the table is much larger
+// than n k, the sum over vertices and partitions of N_i(C(v), l_i(v)).
+void launch_objective0(const Tables& t, int32_t k, int32_t K0, const int32_t* s,
+                       int64_t total_entries, const LabelHist& lh, const int32_t* C,
+                       const int32_t* Lvm, int64_t n,
                        int64_t* acc /* 3 int64: sum s^2, sum hist^2, sum N^2 */,
                        hipStream_t st);
 // Hashed tables: empty every slot; the objective from label histograms
 // (hist: int32[total_labels] scratch) and the slot counts.
 void launch_hash_clear(Tables t, hipStream_t st);
+// singletons: every cell holds 0 or 1, so sum N^2 = n k without a scan.
 void launch_objective0_hashed(const Tables& t, const int32_t* const* dlabels, const int64_t* loff,
                               const int32_t* fmap, int64_t n, int32_t k, int32_t K0,
                               const int32_t* s, int64_t total_labels, int32_t* hist,
-                              int64_t* acc, hipStream_t st);
+                              bool singletons, int64_t* acc, hipStream_t st);
 // In-arc lists: in_ptr (exclusive scan of in-degrees, n + 1) and in_pos
 // (arc positions grouped by head vertex); ac[j] = C[col[j]].
 void launch_in_degree(const int32_t* col, int64_t nnz, int32_t* indeg, hipStream_t st);

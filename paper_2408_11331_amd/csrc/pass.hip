@@ -58,6 +58,19 @@ __device__ inline int32_t group_sum(int32_t x) {
   return x;
 }
 
+// Exclusive prefix sum over the wave's lanes; *total: the wave's sum.
+__device__ inline int32_t wave_excl_scan(int32_t x, int32_t* total) {
+  const int lane = threadIdx.x & 63;
+  int32_t s = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(s, o, 64);
+    if (lane >= o) s += y;
+  }
+  *total = __shfl(s, 63, 64);
+  return s - x;
+}
+
 __device__ inline int64_t wave_sum64(int64_t x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
@@ -114,6 +127,13 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
   constexpr int32_t kInf = 0x7fffffff;
   __shared__ int64_t s_toff[kMaxLdsPart];
   __shared__ int32_t s_L[kMaxLdsPart];
+  // deferred-vertex scorer, per wave: items' first member pair, sums, member
+  // list starts, clusters, and the items of clusters without member lists
+  constexpr int kW = (LIST && G == 64) ? kBlock / 64 : 1;
+  constexpr int kI = (LIST && G == 64) ? 130 : 1;
+  __shared__ int32_t s_ioff[kW][kI], s_isum[kW][kI], s_imst[kW][kI], s_iy[kW][kI],
+      s_ilarge[kW][kI];
+  __shared__ __align__(8) int32_t s_vrow[kW][(LIST && G == 64) ? 64 : 2];
   const int lane = threadIdx.x & (G - 1);
   const int64_t group = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
   const int64_t ngroups = ((int64_t)gridDim.x * kBlock) / G;
@@ -262,35 +282,158 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
           for (int q = 0; q < 4; ++q) lb[q] = sl + 16 * q < k ? row[sl + 16 * q] : 0;
           int32_t s_lo = 0, s_hi = 0, s_v = 0;
           const int nitems = nc + 1;  // item 0: the own cluster; item c + 1: candidate c
-          for (int j0 = 0; j0 < nitems; j0 += 4) {
-            const int it = j0 + sg, ci = it - 1;
-            const int32_t y_lo = __shfl(cand_lo, ci < 0 ? 0 : (ci & 63), 64);
-            const int32_t y_hi = __shfl(cand_hi, ci < 0 ? 0 : (ci & 63), 64);
-            const int32_t y = it == 0 ? cv : (ci < 64 ? y_lo : y_hi);
-            int32_t sum = 0;
-            if (it < nitems) {
-              if (a.members && a.s[y] <= kMemberSumMax) {
-                const int32_t cnt = a.s[y];  // <= 16: one member id per lane
-                const int32_t mid = sl < cnt ? a.members[a.mstart[y] + sl] : 0;
-                for (int32_t mm = 0; mm < cnt; ++mm) {
-                  const int32_t* ru = a.Lvm + (int64_t)__shfl(mid, mm, 16) * k;
+          if (a.members) {
+            // Small clusters (member lists) are scored by their members' label
+            // rows, every member row of every small item in flight at once:
+            // four lanes per (item, member) pair, sixteen pairs a step, the
+            // pair sums added into the item's LDS slot.  The other items
+            // probe the table, one per 16-lane group.
+            const int w = threadIdx.x >> 6;
+            int32_t* ioff = s_ioff[w];
+            int32_t* isum = s_isum[w];
+            int32_t* imst = s_imst[w];
+            int32_t* iy = s_iy[w];
+            int32_t* ilarge = s_ilarge[w];
+            // this lane's items: lane, 64 + lane and, for lane 0, 128
+            const int32_t lo_prev = __shfl(cand_lo, (lane + 63) & 63, 64);
+            const int32_t hi_prev = __shfl(cand_hi, (lane + 63) & 63, 64);
+            const int32_t yA = lane == 0 ? cv : lo_prev;
+            const int32_t yB = lane == 0 ? lo_prev : hi_prev;
+            const int32_t yC = hi_prev;
+            const bool vA = lane < nitems, vB = 64 + lane < nitems, vC = lane == 0 && 128 < nitems;
+            const int32_t zA = vA ? a.s[yA] : 0, zB = vB ? a.s[yB] : 0, zC = vC ? a.s[yC] : 0;
+            const bool smA = vA && zA <= kMemberSumMax, smB = vB && zB <= kMemberSumMax,
+                       smC = vC && zC <= kMemberSumMax;
+            const int32_t mA = smA ? a.mstart[yA] : 0, mB = smB ? a.mstart[yB] : 0,
+                          mC = smC ? a.mstart[yC] : 0;
+            int32_t totA, totB, lgA, lgB;
+            const int32_t exA = wave_excl_scan(smA ? zA : 0, &totA);
+            const int32_t exB = wave_excl_scan(smB ? zB : 0, &totB);
+            const int32_t gA = wave_excl_scan((vA && !smA) ? 1 : 0, &lgA);
+            const int32_t gB = wave_excl_scan((vB && !smB) ? 1 : 0, &lgB);
+            const int32_t cC = __shfl(smC ? zC : 0, 0, 64);
+            const int32_t P = totA + totB + cC;  // member pairs
+            ioff[lane] = exA;
+            ioff[64 + lane] = totA + exB;
+            isum[lane] = 0;
+            isum[64 + lane] = 0;
+            imst[lane] = mA;
+            imst[64 + lane] = mB;
+            iy[lane] = yA;
+            iy[64 + lane] = yB;
+            if (vA && !smA) ilarge[gA] = lane;
+            if (vB && !smB) ilarge[lgA + gB] = 64 + lane;
+            if (lane == 0) {
+              ioff[128] = totA + totB;
+              ioff[129] = P;
+              isum[128] = 0;
+              imst[128] = mC;
+              iy[128] = yC;
+              if (vC && !smC) ilarge[lgA + lgB] = 128;
+            }
+            const int32_t NL = lgA + lgB + __shfl((vC && !smC) ? 1 : 0, 0, 64);
+            __builtin_amdgcn_wave_barrier();
+            // the item of pair p: the last item whose first pair is at or
+            // before p (items without pairs share their successor's offset)
+            auto item_of = [&](int32_t p) {
+              int lo = 0, hi = 128;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (ioff[mid] <= p) lo = mid;
+                else hi = mid - 1;
+              }
+              return lo;
+            };
+            const int li = lane & 3, pq = lane >> 2;
+            int32_t* vrow = s_vrow[w];  // the vertex's row, read by every pair
+            vrow[lane] = lane < k ? row[lane] : 0;
+            __builtin_amdgcn_wave_barrier();
+            if ((k & 1) == 0) {  // rows 8-byte aligned: two partitions a load
+              const int h = k >> 1;
+              const int2* vl = reinterpret_cast<const int2*>(vrow);
+              for (int32_t p0 = 0; p0 < P; p0 += 32) {
+                int32_t sums[2], its[2];
 #pragma unroll
-                  for (int q = 0; q < 4; ++q)
-                    if (sl + 16 * q < k) sum += ru[sl + 16 * q] == lb[q];
+                for (int e = 0; e < 2; ++e) {
+                  const int32_t p = p0 + 16 * e + pq;
+                  sums[e] = 0;
+                  its[e] = -1;
+                  if (p < P) {
+                    const int it = item_of(p);
+                    its[e] = it;
+                    const int32_t u = a.members[imst[it] + (p - ioff[it])];
+                    const int2* ru = reinterpret_cast<const int2*>(a.Lvm + (int64_t)u * k);
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+                      if (li + 4 * t < h) {
+                        const int2 q = ru[li + 4 * t], r = vl[li + 4 * t];
+                        sums[e] += (q.x == r.x) + (q.y == r.y);
+                      }
+                  }
                 }
-              } else {
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                  sums[e] += __shfl_xor(sums[e], 1, 4);
+                  sums[e] += __shfl_xor(sums[e], 2, 4);
+                  if (li == 0 && its[e] >= 0) atomicAdd(&isum[its[e]], sums[e]);
+                }
+              }
+            } else {  // odd k: one partition a load
+              for (int32_t p0 = 0; p0 < P; p0 += 16) {
+                const int32_t p = p0 + pq;
+                int32_t sum = 0, it = -1;
+                if (p < P) {
+                  it = item_of(p);
+                  const int32_t u = a.members[imst[it] + (p - ioff[it])];
+                  const int32_t* ru = a.Lvm + (int64_t)u * k;
+#pragma unroll
+                  for (int t = 0; t < 16; ++t)
+                    if (li + 4 * t < k) sum += ru[li + 4 * t] == vrow[li + 4 * t];
+                }
+                sum += __shfl_xor(sum, 1, 4);
+                sum += __shfl_xor(sum, 2, 4);
+                if (li == 0 && it >= 0) atomicAdd(&isum[it], sum);
+              }
+            }
+            // items of larger clusters: table probes, four items a step
+            for (int32_t j0 = 0; j0 < NL; j0 += 4) {
+              const int32_t jj = j0 + sg;
+              int32_t sum = 0, it = -1;
+              if (jj < NL) {
+                it = ilarge[jj];
+                const int32_t y = iy[it];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                   if (sl + 16 * q < k) sum += count_of(a.t, sl + 16 * q, y, lb[q]);
               }
+              sum = group_sum<16>(sum);
+              if (sl == 0 && it >= 0) isum[it] = sum;
             }
-            sum = group_sum<16>(sum);
-            if (j0 == 0) s_v = __shfl(sum, 0, 64);
-            const int g_lo = lane + 1 - j0, g_hi = lane + 65 - j0;  // groups holding my items
-            const int32_t got_lo = __shfl(sum, (g_lo >= 0 && g_lo < 4) ? g_lo * 16 : 0, 64);
-            const int32_t got_hi = __shfl(sum, (g_hi >= 0 && g_hi < 4) ? g_hi * 16 : 0, 64);
-            if (g_lo >= 0 && g_lo < 4) s_lo = got_lo;
-            if (g_hi >= 0 && g_hi < 4) s_hi = got_hi;
+            __builtin_amdgcn_wave_barrier();
+            s_v = isum[0];
+            s_lo = isum[1 + lane];
+            s_hi = lane < 64 ? isum[65 + lane] : 0;
+            __builtin_amdgcn_wave_barrier();
+          } else {
+            for (int j0 = 0; j0 < nitems; j0 += 4) {
+              const int it = j0 + sg, ci = it - 1;
+              const int32_t y_lo = __shfl(cand_lo, ci < 0 ? 0 : (ci & 63), 64);
+              const int32_t y_hi = __shfl(cand_hi, ci < 0 ? 0 : (ci & 63), 64);
+              const int32_t y = it == 0 ? cv : (ci < 64 ? y_lo : y_hi);
+              int32_t sum = 0;
+              if (it < nitems) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                  if (sl + 16 * q < k) sum += count_of(a.t, sl + 16 * q, y, lb[q]);
+              }
+              sum = group_sum<16>(sum);
+              if (j0 == 0) s_v = __shfl(sum, 0, 64);
+              const int g_lo = lane + 1 - j0, g_hi = lane + 65 - j0;  // groups holding my items
+              const int32_t got_lo = __shfl(sum, (g_lo >= 0 && g_lo < 4) ? g_lo * 16 : 0, 64);
+              const int32_t got_hi = __shfl(sum, (g_hi >= 0 && g_hi < 4) ? g_hi * 16 : 0, 64);
+              if (g_lo >= 0 && g_lo < 4) s_lo = got_lo;
+              if (g_hi >= 0 && g_hi < 4) s_hi = got_hi;
+            }
           }
           const int64_t scv = a.s[cv];
           int64_t bd = INT64_MAX;
@@ -525,7 +668,7 @@ void k_score_tile(PassArgs a) {
         if (tl[r] < 0) continue;
         lo = tl[r];
         const int32_t x = cu[r];
-        if (x == s_c[lo]) continue;
+        if (x == s_c[lo] || s_def[lo]) continue;  // a deferred vertex needs no more keys
         const int32_t key = (lo << 24) | x;
         if (key == prev) continue;
         prev = key;

@@ -420,16 +420,19 @@ __global__ __launch_bounds__(kBlock) void k_sumsq(const int32_t* __restrict__ a,
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)acc, (unsigned long long)s);
 }
 
-// sum over labels l of partition i of |P_i l|^2, with |P_i l| = sum_x N_i(x, l)
-__global__ __launch_bounds__(kBlock) void k_hist_sumsq(Tables t, int32_t K0,
-                                                       int64_t* __restrict__ acc) {
-  const int i = blockIdx.y;
-  const int32_t Li = t.L[i];
+// sum over vertices v and partitions i of N_i(C(v), l_i(v)): a cell whose
+// count is c is met once by each of its c members, so this is the sum over
+// cells of c^2, read from n k cells instead of the whole table
+__global__ __launch_bounds__(kBlock) void k_gather_sumsq(const int32_t* __restrict__ C,
+                                                         const int32_t* __restrict__ Lvm,
+                                                         int64_t n, int32_t k, Tables t,
+                                                         int64_t* __restrict__ acc) {
   int64_t s = 0;
-  for (int64_t l = gtid(); l < Li; l += gstride()) {
-    int64_t h = 0;
-    for (int32_t x = 0; x < K0; ++x) h += t.N[cell(t, i, x, (int32_t)l)];
-    s += h * h;
+  const uint32_t total = (uint32_t)(n * k);  // below 2^31
+  for (uint32_t j = (uint32_t)gtid(); j < total; j += (uint32_t)gstride()) {
+    const uint32_t v = j / (uint32_t)k;
+    const int i = (int)(j - v * (uint32_t)k);
+    s += t.hashed ? hget(t, hkey(t, i, C[v], Lvm[j])) : t.N[cell(t, i, C[v], Lvm[j])];
   }
   s = block_sum<int64_t>(s);
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)acc, (unsigned long long)s);
@@ -559,25 +562,49 @@ __global__ __launch_bounds__(kBlock) void k_canonical_write(const int32_t* __res
 // take ids K0, K0 + 1, ... in label order.  Any injective relabelling leaves
 // every count unchanged; this one puts a vertex's labels and its cluster
 // side by side in the interleaved table.
-__global__ __launch_bounds__(kBlock) void k_align_home(Tables b, int32_t K0,
-                                                       const int64_t* __restrict__ poff,
-                                                       uint64_t* __restrict__ win,
-                                                       int32_t* __restrict__ home,
-                                                       uint64_t* __restrict__ key) {
+// The home of label l of partition i is its most frequent cluster in the
+// sample, the smallest cluster id on ties.  Segment z of the clusters is
+// searched by its own threads, which fold their (count, cluster) best into
+// best[poff[i] + l] packed as count << 32 | ~cluster (zero-filled first).
+__global__ __launch_bounds__(kBlock) void k_align_search(Tables b, int32_t K0, int32_t seg,
+                                                         const int64_t* __restrict__ poff,
+                                                         unsigned long long* __restrict__ best) {
   const int i = blockIdx.y;
   const int32_t Li = b.L[i];
-  for (int64_t l = gtid(); l < Li; l += gstride()) {
-    int32_t bx = 0, bc = -1;
-    for (int32_t x = 0; x < K0; ++x) {
+  const int32_t x0 = (int32_t)blockIdx.z * seg, x1 = min(K0, x0 + seg);
+  for (int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x; l < Li;
+       l += (int64_t)gridDim.x * kBlock) {
+    int32_t bx = x0, bc = -1;
+    for (int32_t x = x0; x < x1; ++x) {
       const int32_t c = b.N[cell(b, i, x, (int32_t)l)];
       if (c > bc) {
         bc = c;
         bx = x;
       }
     }
-    const uint64_t kk = ((uint64_t)(uint32_t)bc << 32) | (uint64_t)(0xffffffffu - (uint32_t)l);
-    home[poff[i] + l] = bx;
-    key[poff[i] + l] = kk;
+    if (bc >= 0)
+      atomicMax(&best[poff[i] + l],
+                ((unsigned long long)(uint32_t)bc << 32) | (0xffffffffu - (uint32_t)bx));
+  }
+}
+
+// home[p] and the label's claim key[p] (count << 32 | ~label) on its home,
+// the largest claim per (partition, cluster) in win
+__global__ __launch_bounds__(kBlock) void k_align_home(const int32_t* __restrict__ L,
+                                                       int32_t K0,
+                                                       const int64_t* __restrict__ poff,
+                                                       uint64_t* __restrict__ win,
+                                                       int32_t* __restrict__ home,
+                                                       uint64_t* __restrict__ key) {
+  const int i = blockIdx.y;
+  for (int64_t l = gtid(); l < L[i]; l += gstride()) {
+    const int64_t p = poff[i] + l;
+    const uint64_t b = key[p];  // the packed best of k_align_search
+    const int32_t bx = (int32_t)(0xffffffffu - (uint32_t)b);
+    const uint32_t bc = (uint32_t)(b >> 32);
+    const uint64_t kk = ((uint64_t)bc << 32) | (uint64_t)(0xffffffffu - (uint32_t)l);
+    home[p] = bx;
+    key[p] = kk;
     atomicMax((unsigned long long*)&win[(int64_t)i * K0 + bx], (unsigned long long)kk);
   }
 }
@@ -701,7 +728,18 @@ void launch_align(const Tables& blocked, int32_t k, int32_t K0, int32_t maxL,
                   int32_t* amap, int32_t* L2, hipStream_t st) {
   dim3 g(grid_for(maxL, kBlock, 256), k);
   k_fill_u64<<<grid_for((int64_t)k * K0, kBlock, 2048), kBlock, 0, st>>>(win, (int64_t)k * K0, 0ull);
-  k_align_home<<<g, kBlock, 0, st>>>(blocked, K0, poff, win, home, key);
+  k_fill_u64<<<grid_for(total_labels, kBlock, 2048), kBlock, 0, st>>>(key, total_labels, 0ull);
+  // enough segments of the clusters (at most 1024) to give the search
+  // about 2^21 threads
+  const int64_t lab_threads = (int64_t)((maxL + kBlock - 1) / kBlock) * kBlock * k;
+  const int64_t nseg = std::max<int64_t>(
+      1, std::min<int64_t>(std::min<int64_t>(K0, 1024),
+                           ((int64_t)1 << 21) / std::max<int64_t>(1, lab_threads)));
+  const int32_t seg = (int32_t)((K0 + nseg - 1) / nseg);
+  dim3 gs((unsigned)((maxL + kBlock - 1) / kBlock), (unsigned)k, (unsigned)((K0 + seg - 1) / seg));
+  k_align_search<<<gs, kBlock, 0, st>>>(blocked, K0, seg, poff,
+                                        reinterpret_cast<unsigned long long*>(key));
+  k_align_home<<<g, kBlock, 0, st>>>(blocked.L, K0, poff, win, home, key);
   k_align_extra<<<g, kBlock, 0, st>>>(blocked.L, K0, poff, win, home, key, extra);
   launch_scan(extra, rank, total_labels, scan_tmp, st);
   k_align_assign<<<g, kBlock, 0, st>>>(blocked.L, K0, poff, home, extra, rank, amap, L2);
@@ -769,14 +807,19 @@ void launch_sizes(const int32_t* C, int64_t n, int32_t K0, int32_t* s, hipStream
   k_sizes<<<grid_for(n, kBlock * 16, 512), kBlock, 0, st>>>(C, n, K0, s);
 }
 
-void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, const int32_t* s,
-                       int64_t total_entries, int64_t* acc, hipStream_t st) {
-  // acc[0] += sum_x s_x^2; acc[1] += sum_i sum_l |P_i l|^2;
-  // acc[2] += sum_i sum_(x,l) N_i(x,l)^2 over all `total_entries` table cells
+void launch_objective0(const Tables& t, int32_t k, int32_t K0, const int32_t* s,
+                       int64_t total_entries, const LabelHist& lh, const int32_t* C,
+                       const int32_t* Lvm, int64_t n, int64_t* acc, hipStream_t st) {
   k_sumsq<<<grid_for(K0, kBlock, 1024), kBlock, 0, st>>>(s, K0, acc);
-  dim3 g(grid_for(maxL, kBlock, 64), k);
-  k_hist_sumsq<<<g, kBlock, 0, st>>>(t, K0, acc + 1);
-  k_sumsq<<<grid_for(total_entries, kBlock, 2048), kBlock, 0, st>>>(t.N, total_entries, acc + 2);
+  launch_fill_i32(lh.hist, lh.total_labels, 0, st);
+  dim3 g(grid_for(n, kBlock * 16, 64), k);
+  k_label_hist<<<g, kBlock, 0, st>>>(lh.dlabels, lh.loff, lh.fmap, lh.lpoff, n, lh.hist);
+  k_sumsq<<<grid_for(lh.total_labels, kBlock, 2048), kBlock, 0, st>>>(lh.hist, lh.total_labels,
+                                                                      acc + 1);
+  if (Lvm && total_entries > 2 * n * (int64_t)k)
+    k_gather_sumsq<<<grid_for(n * k, kBlock, 4096), kBlock, 0, st>>>(C, Lvm, n, k, t, acc + 2);
+  else
+    k_sumsq<<<grid_for(total_entries, kBlock, 2048), kBlock, 0, st>>>(t.N, total_entries, acc + 2);
 }
 
 void launch_hash_clear(Tables t, hipStream_t st) {
@@ -786,13 +829,16 @@ void launch_hash_clear(Tables t, hipStream_t st) {
 void launch_objective0_hashed(const Tables& t, const int32_t* const* dlabels, const int64_t* loff,
                               const int32_t* fmap, int64_t n, int32_t k, int32_t K0,
                               const int32_t* s, int64_t total_labels, int32_t* hist,
-                              int64_t* acc, hipStream_t st) {
+                              bool singletons, int64_t* acc, hipStream_t st) {
   k_sumsq<<<grid_for(K0, kBlock, 1024), kBlock, 0, st>>>(s, K0, acc);
   launch_fill_i32(hist, total_labels, 0, st);
   dim3 g(grid_for(n, kBlock * 16, 64), k);
   k_label_hist<<<g, kBlock, 0, st>>>(dlabels, loff, fmap, t.toff, n, hist);
   k_sumsq<<<grid_for(total_labels, kBlock, 2048), kBlock, 0, st>>>(hist, total_labels, acc + 1);
-  k_slot_sumsq<<<grid_for((int64_t)t.hmask + 1, kBlock * 4, 4096), kBlock, 0, st>>>(t, acc + 2);
+  if (singletons)
+    launch_fill_u64(reinterpret_cast<uint64_t*>(acc + 2), 1, (uint64_t)(n * (int64_t)k), st);
+  else
+    k_slot_sumsq<<<grid_for((int64_t)t.hmask + 1, kBlock * 4, 4096), kBlock, 0, st>>>(t, acc + 2);
 }
 
 void launch_check_symmetric(const int64_t* row_ptr, const int32_t* col, int64_t n,
