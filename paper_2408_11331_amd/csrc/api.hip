@@ -587,7 +587,7 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
   lh.lpoff = dlpoff;
   lh.total_labels = lpoff[k];
   lh.hist = ar.get<int32_t>(lpoff[k]);
-  launch_objective0(S->t, k, K0, S->s, S->total, lh, S->C, S->Lvm, n, S->acc, st);
+  launch_objective0(S->t, k, K0, S->maxL, S->s, S->total, lh, S->C, S->Lvm, n, S->acc, st);
 }
 
 int translate(const std::exception_ptr& ep) {

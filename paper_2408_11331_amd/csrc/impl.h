@@ -34,7 +34,8 @@ struct Ctl {
   int32_t heavy_count;      // vertices deferred by the tiled scorer this pass
   int32_t rescore_count;    // vertices the status kernel left for scoring
   int32_t plist_count;      // proposers of the current pass (k_props)
-  int32_t pad4;
+  int32_t defer_all;        // 1: this pass's vertices all go to the wave-per-vertex
+                            // scorer (most had too many candidates for the tiles)
   int64_t skipped;          // candidate evaluations proven unnecessary (all passes)
   int64_t* trace;           // device int64[max_rounds * 4] or null
 };
@@ -205,11 +206,13 @@ struct LabelHist {
   int64_t total_labels;
   int32_t* hist;
 };
-// acc[0] += sum_x s_x^2; acc[1] += sum_i sum_l |P_i l|^2 (from the label
+// acc[0] += sum_x s_x^2; acc[1] += sum_i sum_l |P_i l|^2 (summed over the
+// table's cells when it has at most n k of them, else from the label
 // histogram); acc[2] += sum over cells of N^2: a scan of the `total_entries`
 // cells, or, when the label rows Lvm are given and the table is much larger
 // than n k, the sum over vertices and partitions of N_i(C(v), l_i(v)).
-void launch_objective0(const Tables& t, int32_t k, int32_t K0, const int32_t* s,
+// maxL: the largest label id bound of the table's partitions.
+void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, const int32_t* s,
                        int64_t total_entries, const LabelHist& lh, const int32_t* C,
                        const int32_t* Lvm, int64_t n,
                        int64_t* acc /* 3 int64: sum s^2, sum hist^2, sum N^2 */,
@@ -355,7 +358,8 @@ struct PassArgs {
 
 constexpr int kDeltaLdsMax = 48 << 10;
 
-constexpr int kPassCounters = 4;    // evaluations, proposals, boundary vertices, skipped
+constexpr int kPassCounters = 5;    // evaluations, proposals, boundary vertices, skipped,
+                                    // boundary vertices with more candidates than a tile holds
 constexpr int kCounterStride = 64;  // int64 words between two counters
 
 constexpr int kCacheCand = 8;  // candidate clusters cached per vertex

@@ -86,9 +86,9 @@ __device__ inline int32_t wave_sum32(int32_t x) {
 // Add the workgroup's totals of the pass counters (all threads call; one
 // atomic per counter and workgroup).
 __device__ inline void flush_counts(const PassArgs& a, int64_t evals, int64_t nprop,
-                                    int64_t boundary, int64_t skipped) {
+                                    int64_t boundary, int64_t skipped, int64_t wide = 0) {
   __shared__ int64_t red[kPassCounters][kBlock / 64];
-  const int64_t v[kPassCounters] = {evals, nprop, boundary, skipped};
+  const int64_t v[kPassCounters] = {evals, nprop, boundary, skipped, wide};
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int c = 0; c < kPassCounters; ++c) {
@@ -113,12 +113,19 @@ __device__ inline void flush_counts(const PassArgs& a, int64_t evals, int64_t np
 // smallest id without any sort.
 // ---------------------------------------------------------------------------
 constexpr int kMaxLdsPart = 256;  // partitions whose table geometry sits in LDS
+constexpr int kTileCandAvg = 8;   // candidates per vertex the tiled scorer's key set holds
+constexpr int kCandSetBits = 8;   // deferred vertex: LDS set of its candidate clusters
+constexpr int kCandSet = 1 << kCandSetBits;
 
 template <int G, bool LIST>
-__global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_score(PassArgs a) {
   if (a.ctl->done) return;
-  // LIST: score only the vertices the tiled scorer deferred
-  const int64_t count = LIST ? (int64_t)a.ctl->heavy_count : a.n;
+  // LIST: the vertices the tiled or list scorer deferred or, in a dense pass
+  // the tiled scorer leaves to this kernel (defer_all), every vertex to
+  // score: the rescoring list, or all vertices when there is none
+  const bool all = LIST && a.ctl->defer_all && !(a.st && a.ctl->rescore_count <= a.sparse_max);
+  const int64_t count =
+      !LIST ? a.n : (all ? (a.st ? (int64_t)a.ctl->rescore_count : a.n) : (int64_t)a.ctl->heavy_count);
   if (LIST && count == 0) return;
   // arcs per lane held in registers; the deferred-vertex scorer (one wave
   // per vertex) holds 512, for the highest degrees
@@ -134,6 +141,9 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
   __shared__ int32_t s_ioff[kW][kI], s_isum[kW][kI], s_imst[kW][kI], s_iy[kW][kI],
       s_ilarge[kW][kI];
   __shared__ __align__(8) int32_t s_vrow[kW][(LIST && G == 64) ? 64 : 2];
+  __shared__ int32_t s_cset[kW][(LIST && G == 64) ? kCandSet : 1];
+  __shared__ int32_t s_clist[kW][(LIST && G == 64) ? 128 : 1];
+  __shared__ int32_t s_ccount[kW];
   const int lane = threadIdx.x & (G - 1);
   const int64_t group = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
   const int64_t ngroups = ((int64_t)gridDim.x * kBlock) / G;
@@ -147,9 +157,9 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
   const bool lds_geom = k <= kMaxLdsPart;
 
   int64_t evals = 0;
-  int32_t nprop = 0, boundary = 0;
+  int32_t nprop = 0, boundary = 0, wide = 0;
   for (int64_t idx = group; idx < count; idx += ngroups) {
-    const int64_t v = LIST ? (int64_t)a.heavy[idx] : idx;
+    const int64_t v = !LIST ? idx : (all ? (a.st ? (int64_t)a.rlist[idx] : idx) : (int64_t)a.heavy[idx]);
     const int32_t cv = a.C[v];
     const int64_t beg = a.row_ptr[v], end = a.row_ptr[v + 1];
     const bool fits = end - beg <= (int64_t)G * R;
@@ -244,28 +254,55 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
 
     if constexpr (LIST && G == 64) {
       if (fits && kfits) {
-        // a deferred vertex: its candidate clusters collected in increasing
-        // id (lane j holds candidates j and 64 + j), then its own cluster and
-        // the candidates scored four at a time by 16-lane groups, and the
-        // smallest (gain, cluster id) taken by a wave reduction
-        int32_t cand_lo = kInf, cand_hi = kInf, nc = 0;
-        bool many = false;  // more than 128 candidates: the general path below
-        for (;;) {
-          int32_t m = kInf;
+        // a deferred vertex: its distinct candidate clusters collected in a
+        // per-wave LDS hash set and compacted (lane j holds candidates j and
+        // 64 + j, in no particular order: every argmin breaks ties by
+        // cluster id), then its own cluster and the candidates scored, and
+        // the smallest (gain, cluster id) taken by a wave reduction
+        const int w = threadIdx.x >> 6;
+        int32_t* cset = s_cset[w];
+        for (int j = lane; j < kCandSet; j += 64) cset[j] = -1;
+        if (lane == 0) s_ccount[w] = 0;
+        __builtin_amdgcn_wave_barrier();
 #pragma unroll
-          for (int r = 0; r < R; ++r) m = min(m, x[r]);
-          m = group_min<64>(m);
-          if (m == kInf) break;
-          if (nc == 128) {
-            many = true;
-            break;
+        for (int r = 0; r < R; ++r) {
+          const int32_t y = x[r];
+          if (y == kInf) continue;
+          uint32_t h = ((uint32_t)y * 2654435761u) >> (32 - kCandSetBits);
+          for (int q = 0; q < kCandSet; ++q) {  // bounded: a full set ends it
+            int32_t cur = cset[h];
+            if (cur == -1) {
+              cur = atomicCAS(&cset[h], -1, y);
+              if (cur == -1) {
+                atomicAdd(&s_ccount[w], 1);
+                break;
+              }
+            }
+            if (cur == y) break;
+            h = (h + 1) & (kCandSet - 1);
           }
-          if (lane == nc) cand_lo = m;
-          else if (lane == nc - 64) cand_hi = m;
-          ++nc;
+        }
+        __builtin_amdgcn_wave_barrier();
+        int32_t nc = s_ccount[w];
+        const bool many = nc > 128;  // more than 128 candidates: the general path below
+        int32_t cand_lo = kInf, cand_hi = kInf;
+        if (!many) {
+          int32_t mine = 0, keys[kCandSet / 64];
 #pragma unroll
-          for (int r = 0; r < R; ++r)
-            if (x[r] == m) x[r] = kInf;
+          for (int q = 0; q < kCandSet / 64; ++q) {
+            keys[q] = cset[lane + 64 * q];
+            mine += keys[q] != -1;
+          }
+          int32_t total;
+          int32_t pos = wave_excl_scan(mine, &total);
+          int32_t* clist = s_clist[w];
+#pragma unroll
+          for (int q = 0; q < kCandSet / 64; ++q)
+            if (keys[q] != -1) clist[pos++] = keys[q];
+          __builtin_amdgcn_wave_barrier();
+          cand_lo = lane < nc ? clist[lane] : kInf;
+          cand_hi = 64 + lane < nc ? clist[64 + lane] : kInf;
+          __builtin_amdgcn_wave_barrier();
         }
         if (!many) {
           if (a.dirty) {  // the candidate set, cached for later passes
@@ -288,7 +325,6 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
             // four lanes per (item, member) pair, sixteen pairs a step, the
             // pair sums added into the item's LDS slot.  The other items
             // probe the table, one per 16-lane group.
-            const int w = threadIdx.x >> 6;
             int32_t* ioff = s_ioff[w];
             int32_t* isum = s_isum[w];
             int32_t* imst = s_imst[w];
@@ -460,6 +496,7 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
           if (lane == 0) {
             evals += nc;
             boundary += 1;
+            wide += nc > kTileCandAvg;
             const bool p = bd < 0;
             a.prop[v] = p ? bx : kNone;
             if (p) {
@@ -522,6 +559,7 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
     if (lane == 0) {
       evals += ncand;
       boundary += ncand > 0;
+      wide += ncand > kTileCandAvg;
       const bool p = ncand > 0 && bestd < 0;
       a.prop[v] = p ? bestx : kNone;
       if (p) {
@@ -530,7 +568,7 @@ __global__ __launch_bounds__(kBlock) void k_score(PassArgs a) {
       }
     }
   }
-  flush_counts(a, evals, nprop, boundary, 0);
+  flush_counts(a, evals, nprop, boundary, 0, wide);
 }
 
 // ---------------------------------------------------------------------------
@@ -560,6 +598,7 @@ constexpr int kProbeLanes = 16;
 constexpr int kProbeRegs = 64 / kProbeLanes;  // labels per lane when k <= 64
 constexpr int kProbeBatch = 4;
 static_assert(kMemberSumMax <= kProbeLanes, "member ids of a small cluster fit one probe group");
+static_assert(kSetSlots / kBlock == kTileCandAvg, "the tile's key set per vertex");
 
 template <int CN, int TK>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8)))
@@ -580,10 +619,13 @@ void k_score_tile(PassArgs a) {
   const bool kfits = k <= kProbeRegs * kProbeLanes;
   const int g = t / kProbeLanes, lane = t % kProbeLanes;
   int64_t evals = 0;
-  int32_t nprop = 0, boundary = 0;
+  int32_t nprop = 0, boundary = 0, wide = 0;
   const int64_t ntiles = (a.n + kBlock - 1) / kBlock;
-  // passes with few vertices to rescore are left to the list scorer
+  // passes with few vertices to rescore are left to the list scorer, and
+  // passes whose vertices mostly have more candidates than a tile holds to
+  // the wave-per-vertex scorer
   if (a.st && a.ctl->rescore_count <= a.sparse_max) return;
+  if (a.ctl->defer_all) return;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t v0 = tile * kBlock;
     const int nv = (int)min((int64_t)kBlock, a.n - v0);
@@ -720,6 +762,7 @@ void k_score_tile(PassArgs a) {
       } else {
         evals += nc;
         boundary += 1;
+        wide += nc > kTileCandAvg;
       }
     }
     s_cur[t] = coff + 1;
@@ -881,7 +924,7 @@ void k_score_tile(PassArgs a) {
     }
     __syncthreads();
   }
-  flush_counts(a, evals, nprop, boundary, 0);
+  flush_counts(a, evals, nprop, boundary, 0, wide);
 }
 
 // ---------------------------------------------------------------------------
@@ -1003,7 +1046,7 @@ __global__ __launch_bounds__(kBlock) void k_score_list(PassArgs a) {
   const int64_t ngroups = ((int64_t)gridDim.x * kBlock) / G;
   const int32_t k = a.k;
   int64_t evals = 0;
-  int32_t nprop = 0, boundary = 0;
+  int32_t nprop = 0, boundary = 0, wide = 0;
   for (int64_t idx = group; idx < count; idx += ngroups) {
     const int64_t v = a.rlist[idx];
     const int32_t cv = a.C[v];
@@ -1110,6 +1153,7 @@ __global__ __launch_bounds__(kBlock) void k_score_list(PassArgs a) {
     if (lane == 0) {
       evals += nc;
       boundary += 1;
+      wide += nc > kTileCandAvg;
       const bool p = bd < 0;
       a.prop[v] = p ? bx : kNone;
       if (p) {
@@ -1119,7 +1163,7 @@ __global__ __launch_bounds__(kBlock) void k_score_list(PassArgs a) {
       a.slack[v] = p ? -1 : (int32_t)min(bd, (int64_t)INT32_MAX);
     }
   }
-  flush_counts(a, evals, nprop, boundary, 0);
+  flush_counts(a, evals, nprop, boundary, 0, wide);
 }
 
 __global__ void k_begin(Ctl* ctl, int64_t* pc) {
@@ -1134,6 +1178,9 @@ __global__ void k_begin(Ctl* ctl, int64_t* pc) {
   ctl->nprop = (int32_t)c[1];
   ctl->boundary += c[2];
   ctl->skipped += c[3];
+  // most boundary vertices had more candidates than the tiles hold: the
+  // next pass skips the tiled scorer and scores every vertex by the wave
+  ctl->defer_all = 2 * c[4] > c[2] ? 1 : 0;
   ctl->passes += 1;
   ctl->evals += ctl->pass_evals;
   ctl->pass_evals = 0;

@@ -420,6 +420,21 @@ __global__ __launch_bounds__(kBlock) void k_sumsq(const int32_t* __restrict__ a,
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)acc, (unsigned long long)s);
 }
 
+// sum over labels l of partition i of |P_i l|^2, with |P_i l| = sum_x N_i(x, l)
+__global__ __launch_bounds__(kBlock) void k_hist_sumsq(Tables t, int32_t K0,
+                                                       int64_t* __restrict__ acc) {
+  const int i = blockIdx.y;
+  const int32_t Li = t.L[i];
+  int64_t s = 0;
+  for (int64_t l = gtid(); l < Li; l += gstride()) {
+    int64_t h = 0;
+    for (int32_t x = 0; x < K0; ++x) h += t.N[cell(t, i, x, (int32_t)l)];
+    s += h * h;
+  }
+  s = block_sum<int64_t>(s);
+  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)acc, (unsigned long long)s);
+}
+
 // sum over vertices v and partitions i of N_i(C(v), l_i(v)): a cell whose
 // count is c is met once by each of its c members, so this is the sum over
 // cells of c^2, read from n k cells instead of the whole table
@@ -807,15 +822,20 @@ void launch_sizes(const int32_t* C, int64_t n, int32_t K0, int32_t* s, hipStream
   k_sizes<<<grid_for(n, kBlock * 16, 512), kBlock, 0, st>>>(C, n, K0, s);
 }
 
-void launch_objective0(const Tables& t, int32_t k, int32_t K0, const int32_t* s,
+void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, const int32_t* s,
                        int64_t total_entries, const LabelHist& lh, const int32_t* C,
                        const int32_t* Lvm, int64_t n, int64_t* acc, hipStream_t st) {
   k_sumsq<<<grid_for(K0, kBlock, 1024), kBlock, 0, st>>>(s, K0, acc);
-  launch_fill_i32(lh.hist, lh.total_labels, 0, st);
-  dim3 g(grid_for(n, kBlock * 16, 64), k);
-  k_label_hist<<<g, kBlock, 0, st>>>(lh.dlabels, lh.loff, lh.fmap, lh.lpoff, n, lh.hist);
-  k_sumsq<<<grid_for(lh.total_labels, kBlock, 2048), kBlock, 0, st>>>(lh.hist, lh.total_labels,
-                                                                      acc + 1);
+  if (total_entries <= n * (int64_t)k) {  // a small table: label sizes from its cells
+    dim3 g(grid_for(maxL, kBlock, 64), k);
+    k_hist_sumsq<<<g, kBlock, 0, st>>>(t, K0, acc + 1);
+  } else {  // a large one: from the labels, n k reads
+    launch_fill_i32(lh.hist, lh.total_labels, 0, st);
+    dim3 g(grid_for(n, kBlock * 16, 64), k);
+    k_label_hist<<<g, kBlock, 0, st>>>(lh.dlabels, lh.loff, lh.fmap, lh.lpoff, n, lh.hist);
+    k_sumsq<<<grid_for(lh.total_labels, kBlock, 2048), kBlock, 0, st>>>(lh.hist, lh.total_labels,
+                                                                        acc + 1);
+  }
   if (Lvm && total_entries > 2 * n * (int64_t)k)
     k_gather_sumsq<<<grid_for(n * k, kBlock, 4096), kBlock, 0, st>>>(C, Lvm, n, k, t, acc + 2);
   else
