@@ -508,7 +508,7 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
     launch_fill_u64(reinterpret_cast<uint64_t*>(S->acc), 3, 0ull, st);
     int32_t* hist = ar.get<int32_t>(sumL);
     launch_objective0_hashed(t, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, S->s, sumL,
-                             hist, init == nullptr, S->acc, st);
+                             hist, K0 == n, S->acc, st);
     return;
   }
   // Blocked tables with dense label ids: the final tables when the labels

@@ -220,7 +220,7 @@ void launch_objective0(const Tables& t, int32_t k, int32_t K0, int32_t maxL, con
 // Hashed tables: empty every slot; the objective from label histograms
 // (hist: int32[total_labels] scratch) and the slot counts.
 void launch_hash_clear(Tables t, hipStream_t st);
-// singletons: every cell holds 0 or 1, so sum N^2 = n k without a scan.
+// singletons (K0 = n): every cell holds 0 or 1, so sum N^2 = n k without a scan.
 void launch_objective0_hashed(const Tables& t, const int32_t* const* dlabels, const int64_t* loff,
                               const int32_t* fmap, int64_t n, int32_t k, int32_t K0,
                               const int32_t* s, int64_t total_labels, int32_t* hist,

@@ -1178,9 +1178,10 @@ __global__ void k_begin(Ctl* ctl, int64_t* pc) {
   ctl->nprop = (int32_t)c[1];
   ctl->boundary += c[2];
   ctl->skipped += c[3];
-  // most boundary vertices had more candidates than the tiles hold: the
-  // next pass skips the tiled scorer and scores every vertex by the wave
-  ctl->defer_all = 2 * c[4] > c[2] ? 1 : 0;
+  // most boundary vertices had more candidates than the tiles hold, and
+  // many on average (the counts fall fast once clusters merge): the next
+  // pass skips the tiled scorer and scores every vertex by the wave
+  ctl->defer_all = (2 * c[4] > c[2] && c[0] > 12 * c[2]) ? 1 : 0;
   ctl->passes += 1;
   ctl->evals += ctl->pass_evals;
   ctl->pass_evals = 0;
