@@ -116,6 +116,27 @@ def bench_batch(args):
     assert info["rc"] == 0 and all(pb.status[j] == 0 for j in range(count))
     stats = [pb.stats[j].as_dict() for j in range(count)]
     batch_out = [pb.output(j).cpu().numpy() for j in range(count)]
+    # every instance against the oracle's stored result (when the stored
+    # workload is this one)
+    checked = 0
+    gp = os.path.join(ROOT, "tests", "golden", "sbm_batch.json")
+    if count == 4096 and os.path.exists(gp):
+        g = json.load(open(gp))
+        cols = g["columns"]
+        for row, inst, o, st in zip(g["rows"], insts, batch_out, stats):
+            rec = dict(zip(cols, row))
+            assert inst.digest()[:16] == rec["digest16"], "instance regenerated differently"
+            got = hashlib.sha256(np.ascontiguousarray(o, "<i4").tobytes()).hexdigest()[:16]
+            assert got == rec["out_sha16"], f"instance {rec['index']} differs from the oracle"
+            for key in cols[3:]:
+                assert st[key] == rec[key], (rec["index"], key)
+            checked += 1
+        log(f"all {checked} batched solves equal the oracle's stored results")
+    # roofline of the persistent launch: each instance's passes times its
+    # per-pass algorithmic bytes, over the launch's time on the stream
+    alg = sum(st["passes"] * pass_bytes(i) for st, i in zip(stats, insts))
+    launch_s = info["ms_total"] / 1e3
+    achieved = alg / launch_s / 1e9
     # one at a time, same instances, once
     t0 = time.perf_counter()
     same = True
@@ -144,6 +165,11 @@ def bench_batch(args):
         "one_at_a_time": {"solves_per_s": count / el1, "seconds": el1,
                           "identical_outputs": bool(same)},
         "speedup_vs_one_at_a_time": el1 / el,
+        "oracle_checked": checked,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_formula": "sum over instances of passes x (4nk + 8(n+1) + 4nnz + 8n)",
+                     "launch_ms": info["ms_total"]},
     }
 
 
@@ -244,20 +270,32 @@ def boundary_bytes(inst, passes, boundary, accepted):
 
 
 def host_cpu():
-    """The host's processor model and the cores this process may use."""
-    model = ""
+    """The host's processor model, its logical and physical cores (as lscpu
+    counts them from /proc/cpuinfo) and the cores this process may use (as
+    nproc reports them)."""
+    model, cores, phys, core = "", set(), None, None
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
+            key, _, val = line.partition(":")
+            key, val = key.strip(), val.strip()
+            if key == "model name" and not model:
+                model = val
+            elif key == "physical id":
+                phys = val
+            elif key == "core id":
+                core = val
+            elif not key:
+                if phys is not None and core is not None:
+                    cores.add((phys, core))
+                phys = core = None
     except OSError:
         pass
     try:
         usable = len(os.sched_getaffinity(0))
     except AttributeError:
         usable = os.cpu_count()
-    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+    return {"model": model, "logical_cpus": os.cpu_count(), "physical_cores": len(cores) or None,
+            "usable_cpus_nproc": usable}
 
 
 def golden_record(inst, init_kind, digest):
@@ -364,6 +402,11 @@ def main():
 
     import paper_2408_11331_amd as mcc
     mcc.lib()
+    if args.calibrate:
+        x = torch.ones(128 << 20, dtype=torch.int32, device="cuda")
+        y = x + 0  # reads and writes 512 MiB once
+        torch.cuda.synchronize()
+        del x, y
     if args.workload in ("sbm_batch", "served"):
         rec = bench_batch(args) if args.workload == "sbm_batch" else bench_served(args)
         print(json.dumps(rec), flush=True)
@@ -371,11 +414,6 @@ def main():
     dev = "cuda"
     t0 = time.perf_counter()
     log(f"generating {args.workload}")
-    if args.calibrate:
-        x = torch.ones(128 << 20, dtype=torch.int32, device=dev)
-        y = x + 0  # reads and writes 512 MiB once
-        torch.cuda.synchronize()
-        del x, y
     inst = make_workload(args.workload, args.n, dev, args.cache or None)
     log(f"generated n={inst.n} nnz={inst.nnz} k={inst.k} in {time.perf_counter() - t0:.1f} s")
     D = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
