@@ -16,8 +16,9 @@
  *    e.g. a torch tensor's data_ptr), unless a comment says "host".  The
  *    caller owns every buffer; the library keeps no pointer to them after a
  *    call returns.  Its own workspace is kept between calls, per device and
- *    stream (at most 64 GiB in total; mcc_release_workspace frees it), so
- *    that repeated calls allocate nothing.  When an allocation fails, the
+ *    shared by the calls of every stream (at most 64 GiB in total;
+ *    mcc_release_workspace frees it), so that repeated calls allocate
+ *    nothing.  When an allocation fails, the
  *    idle workspace the library keeps on that device (any stream) is freed
  *    and the allocation tried once more before MCC_ENOMEM is returned.
  *  - `stream` is a hipStream_t passed as void*; NULL means the default
@@ -338,9 +339,9 @@ int mcc_batch_tune(const mcc_problem* probs, int32_t count, const mcc_batch_opts
  * slot's table are not foreseen).  The exact figure of a finished call is
  * opts->workspace_bytes.
  *
- * mcc_workspace_held: the workspace the library keeps, between calls, for
- * `stream` on the current device (0 if none): what calls on that stream
- * hold when idle.
+ * mcc_workspace_held: the workspace the library keeps, between calls, on
+ * the current device (0 if none), shared by the calls of every stream: what
+ * the library holds there when no call is running.
  *
  * All three return 0 or MCC_EINVAL (NULL bytes, sizes out of range);
  * mcc_workspace_held may return MCC_EDEVICE.
@@ -349,7 +350,7 @@ int mcc_workspace_bound(int64_t n, int64_t nnz, int32_t k, int64_t max_label, in
                         uint32_t flags, int64_t* bytes);
 int mcc_batch_workspace_bytes(const mcc_problem* probs, int32_t count,
                               const mcc_batch_opts* opts, int64_t* bytes);
-int mcc_workspace_held(void* stream, int64_t* bytes);
+int mcc_workspace_held(int64_t* bytes);
 
 /* Write a tune table as text to `path` / read it back.  Host only.
  * Returns 0, MCC_EINVAL (NULL argument, unreadable or malformed file,

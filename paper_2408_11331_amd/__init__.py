@@ -144,7 +144,7 @@ def lib():
         L.mcc_batch_workspace_bytes.argtypes = [ctypes.POINTER(Problem), i32,
                                                 ctypes.POINTER(BatchOpts), p]
         L.mcc_batch_workspace_bytes.restype = ctypes.c_int
-        L.mcc_workspace_held.argtypes = [p, p]
+        L.mcc_workspace_held.argtypes = [p]
         L.mcc_workspace_held.restype = ctypes.c_int
         for f in ("mcc_compare", "mcc_split_join_matrix", "mcc_group_from_distances",
                   "mcc_group_partitions", "mcc_release_workspace"):
@@ -461,10 +461,11 @@ def batch_workspace_bytes(problems, *, lanes=0, wg_per_cu=0, tune=None, tune_cac
     return b.value
 
 
-def workspace_held(stream=None) -> int:
-    """Workspace the library keeps between calls for this stream (host)."""
+def workspace_held() -> int:
+    """Workspace the library keeps between calls on the current device,
+    shared by every stream (host)."""
     b = ctypes.c_int64(0)
-    _check(lib().mcc_workspace_held(_stream_ptr(stream), ctypes.byref(b)))
+    _check(lib().mcc_workspace_held(ctypes.byref(b)))
     return b.value
 
 

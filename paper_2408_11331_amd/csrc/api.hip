@@ -51,14 +51,15 @@ struct Status {
   int code;
 };
 
-// Workspace chunks kept between calls, per (device, stream): an arena takes
-// a cached chunk of its stream when it needs one and gives back what it took
-// when it ends, so steady-state calls allocate and free nothing (allocation
-// and free calls cost about a tenth of a millisecond each), and arenas
-// nested on one stream share the cache instead of each allocating anew.
-// Reuse on the same stream is ordered by the stream.  Chunks beyond
-// kCachedMax bytes in total are freed on return; mcc_release_workspace frees
-// the rest.
+// Workspace chunks kept between calls, per device: an arena takes a cached
+// chunk when it needs one and gives back what it took when it ends, so
+// steady-state calls allocate and free nothing (allocation and free calls
+// cost about a tenth of a millisecond each, large frees synchronise the
+// device), and arenas nested in one call share the cache instead of each
+// allocating anew.  An arena drains its stream before it returns its
+// chunks, so a cached chunk is idle and any stream may take it: calls on
+// several streams share one cache.  Chunks beyond kCachedMax bytes in total
+// are freed on return; mcc_release_workspace frees the rest.
 struct Chunk {
   void* p;
   size_t size;
@@ -66,7 +67,7 @@ struct Chunk {
 
 struct ChunkCache {
   std::mutex m;
-  std::map<std::pair<int, hipStream_t>, std::vector<Chunk>> free;
+  std::map<int, std::vector<Chunk>> free;  // per device
   size_t bytes = 0;
 };
 
@@ -82,7 +83,7 @@ void release_cached(int dev) {
   ChunkCache& c = chunk_cache();
   std::lock_guard<std::mutex> lock(c.m);
   for (auto it = c.free.begin(); it != c.free.end();) {
-    if (it->first.first != dev) {
+    if (it->first != dev) {
       ++it;
       continue;
     }
@@ -111,7 +112,7 @@ class Arena {
     if (fixed_ || used_.empty()) return;
     ChunkCache& c = chunk_cache();
     std::lock_guard<std::mutex> lock(c.m);
-    std::vector<Chunk>& keep = c.free[{dev_, st_}];
+    std::vector<Chunk>& keep = c.free[dev_];
     for (const Chunk& k : used_) {
       if (c.bytes + k.size <= kCachedMax) {
         keep.push_back(k);
@@ -158,14 +159,14 @@ class Arena {
   }
 
  private:
-  // The smallest cached chunk of the stream of at least `size` bytes, else
+  // The smallest cached chunk of the device of at least `size` bytes, else
   // a new one.
   Chunk chunk(size_t size) {
     Chunk k{nullptr, 0};
     {
       ChunkCache& c = chunk_cache();
       std::lock_guard<std::mutex> lock(c.m);
-      auto it = c.free.find({dev_, st_});
+      auto it = c.free.find(dev_);
       if (it != c.free.end()) {
         std::vector<Chunk>& v = it->second;
         size_t best = v.size();
@@ -1805,7 +1806,7 @@ int mcc_release_workspace(void) {
   (void)hipGetDevice(&cur);
   int rc = MCC_OK;
   for (auto& kv : c.free) {
-    if (hipSetDevice(kv.first.first) != hipSuccess) rc = MCC_EDEVICE;
+    if (hipSetDevice(kv.first) != hipSuccess) rc = MCC_EDEVICE;
     for (const Chunk& k : kv.second)
       if (hipFree(k.p) != hipSuccess) rc = MCC_EDEVICE;
   }
@@ -1815,14 +1816,14 @@ int mcc_release_workspace(void) {
   return rc;
 }
 
-int mcc_workspace_held(void* stream, int64_t* bytes) {
+int mcc_workspace_held(int64_t* bytes) {
   if (!bytes) return MCC_EINVAL;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return MCC_EDEVICE;
   ChunkCache& c = chunk_cache();
   std::lock_guard<std::mutex> lock(c.m);
   int64_t b = 0;
-  auto it = c.free.find({dev, (hipStream_t)stream});
+  auto it = c.free.find(dev);
   if (it != c.free.end())
     for (const Chunk& k : it->second) b += (int64_t)k.size;
   *bytes = b;

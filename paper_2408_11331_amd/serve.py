@@ -16,10 +16,10 @@ requests one at a time.  Calls on different workers' streams overlap on the
 GPU, so requests that arrive while others are being solved start at once.
 
 Admission keeps device memory within a budget: the resident pool, the
-workspace each worker's stream keeps between calls (the library retains it
-and reports it, ``mcc_workspace_held``), and for each call in flight its
-whole workspace and outputs, counted as if none of the retained workspace
-could be reused.  A call's workspace is taken from the library's own sizing
+workspace the library keeps between calls (shared by the workers' streams;
+the library reports it, ``mcc_workspace_held``), and for each call in
+flight its whole workspace and outputs, counted as if none of the retained
+workspace could be reused.  A call's workspace is taken from the library's own sizing
 (``mcc_workspace_bound``, ``mcc_batch_workspace_bytes``) until a solve of
 the same entry has reported its exact figure (``workspace_bytes``).
 
@@ -231,8 +231,8 @@ class GpuBackend:
     def make_stream(self):
         return self.torch.cuda.Stream()  # default priority
 
-    def held(self, stream) -> int:
-        return self.mcc.workspace_held(stream)
+    def held(self) -> int:
+        return self.mcc.workspace_held()
 
     def release(self) -> None:
         """Free the library's idle workspace (no call may be in flight)."""
@@ -276,10 +276,8 @@ class GpuBackend:
 class Server:
     """Admission queue plus worker threads that own one stream each.
 
-    Each worker first warms its stream up (one solve of the smallest entry
-    of its kind, and for small workers one batched call, which sets up the
-    batched launch's graph), so that the first requests pay no set-up; the
-    constructor returns once every worker is ready."""
+    Each worker first warms up (``_warm``), so that the first requests pay
+    no set-up; the constructor returns once every worker is ready."""
 
     def __init__(self, pool: Pool, budget_bytes: int = 64 << 30, large_n: int = 50_000,
                  max_batch: int = 512, small_workers: int = 4, large_workers: int = 2,
@@ -295,7 +293,7 @@ class Server:
         self.cv = threading.Condition()
         self.running = True
         self.completed: List[Request] = []
-        self.retained = {}      # worker -> workspace its stream keeps (library figure)
+        self.retained = 0       # workspace the library keeps on the device (its figure)
         self.growth = {}        # worker -> bytes its call in flight may add
         self.blocked = {}       # worker -> arrival of its request waiting for memory
         self.peak_in_use = 0
@@ -307,7 +305,6 @@ class Server:
         self.kinds = kinds
         ready = threading.Barrier(len(kinds) + 1)
         for w, large in enumerate(kinds):
-            self.retained[w] = 0
             self.growth[w] = 0
             self.blocked[w] = None
             self.threads.append(threading.Thread(target=self._worker, args=(w, large, warm, ready),
@@ -323,8 +320,7 @@ class Server:
     def in_use(self) -> int:
         """Bytes accounted for: resident pool, retained workspaces, calls in
         flight (caller holds the lock)."""
-        return (self.pool.resident_bytes + sum(self.retained.values()) +
-                sum(self.growth.values()))
+        return self.pool.resident_bytes + self.retained + sum(self.growth.values())
 
     # -- client side ----------------------------------------------------------
     def submit(self, entry: int, rid: int = 0) -> Request:
@@ -344,16 +340,20 @@ class Server:
 
     # -- workers ----------------------------------------------------------------
     def _warm(self, w: int, large: bool, stream):
+        """One solve of an entry of the worker's kind (the largest for large
+        workers, so that the workspace kept between calls is sized for any
+        request; the smallest for small ones) and, for small workers, one
+        batched call (it sets up the batched launch's graph)."""
         entries = self.pool.entries
         mine = [e for e in entries if (e.n > self.large_n) == large]
         if not mine:
             return
-        e = min(mine, key=lambda x: x.n)
+        e = max(mine, key=lambda x: x.n) if large else min(mine, key=lambda x: x.n)
         self.backend.solve([Request(e.index)], stream)
         if not large and e.t_batch is not None:
             self.backend.solve([Request(e.index) for _ in range(3)], stream, batched=True)
         with self.cv:
-            self.retained[w] = self.backend.held(stream)
+            self.retained = self.backend.held()
 
     def _worker(self, w: int, large: bool, warm: bool, ready):
         stream = self.backend.make_stream()
@@ -379,15 +379,14 @@ class Server:
                     idle = not any(self.growth.values())
                     picked, growth, reclaim, batched = admit(
                         self.queue, entries, self.budget, self.in_use(),
-                        sum(self.retained.values()), self.large_n, large, self.max_batch, bws,
+                        self.retained, self.large_n, large, self.max_batch, bws,
                         idle=idle, before=before,
                         workers=self.kinds.count(large))
                     if picked:
                         self.blocked[w] = None
                         if reclaim:
                             self.backend.release()
-                            for v in self.retained:
-                                self.retained[v] = 0
+                            self.retained = 0
                             self.reclaims += 1
                         break
                     head = next((r for r in self.queue
@@ -409,7 +408,7 @@ class Server:
             held = None
             try:
                 self.backend.solve(picked, stream, batched)
-                held = self.backend.held(stream)
+                held = self.backend.held()
             except Exception as e:  # reported per request, the server keeps going
                 for r in picked:
                     r.error = f"{type(e).__name__}: {e}"
@@ -417,7 +416,7 @@ class Server:
             with self.cv:
                 self.growth[w] = 0
                 if held is not None:
-                    self.retained[w] = held
+                    self.retained = held
                 for r in picked:
                     r.done_at = t1
                     self.completed.append(r)
@@ -467,7 +466,7 @@ def run_served(pool: Pool, weights, rate: float, count: int, seed: int = 0,
     srv.close()
     summ = latency_summary(reqs)
     summ.update(batches=srv.batches, batched_calls=srv.batched_calls, reclaims=srv.reclaims, peak_accounted_bytes=srv.peak_in_use,
-                retained_bytes=sum(srv.retained.values()), budget_bytes=srv.budget,
+                retained_bytes=srv.retained, budget_bytes=srv.budget,
                 resident_bytes=pool.resident_bytes)
     return reqs, summ
 

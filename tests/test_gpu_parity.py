@@ -321,6 +321,26 @@ def test_determinism_and_resume(mcc):
     assert np.array_equal(out, a[0]) and st["passes"] == 1 and st["moves"] == 0
 
 
+def test_apply_run_twice_on_large_first_passes(mcc):
+    """The batch apply on first passes that move most vertices (hundreds of
+    thousands of updates through the workgroup tables and the global
+    counters) gives the same counts, objective and trace on every run: the
+    hashed apply (singleton start) and the dense ones (first partition)."""
+    announce("apply determinism: lfr n=300000 k=16, singleton and p0, twice each")
+    inst = synth.lfr(n=300_000, k=16, w=77)
+    for init, kw in ((None, {}), ("inst", {}), ("inst", {"flags": mcc.MCC_F_SYMMETRIC})):
+        first = [run_gpu(mcc, inst, init, max_rounds=1, **kw) for _ in range(2)]
+        whole = [run_gpu(mcc, inst, init, **kw) for _ in range(2)]
+        for a, b in (first, whole):
+            assert np.array_equal(a[0], b[0])
+            assert np.array_equal(a[2], b[2])
+            for key in KEYS:
+                assert a[1][key] == b[1][key], key
+        assert first[0][1]["moves"] > 50_000  # a large first pass
+        # the objective each pass reports is the definition's value
+        assert whole[0][1]["objective"] == oracle.objective(whole[0][0], inst.labels)
+
+
 def test_error_paths(mcc):
     announce("errors")
     import torch

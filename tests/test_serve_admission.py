@@ -155,18 +155,18 @@ def test_requests_after_a_blocked_one_wait():
 
 class FakeBackend:
     """Stands in for the GPU: returns the vertex ids as the answer and keeps
-    a made-up retained workspace per stream."""
+    a made-up retained workspace."""
 
     def __init__(self, pool, delay=0.002):
         self.pool, self.delay = pool, delay
         self.calls = []
-        self.keep = {}
+        self.kept = 0
 
     def make_stream(self):
         return object()
 
-    def held(self, stream):
-        return self.keep.get(id(stream), 0)
+    def held(self):
+        return self.kept
 
     def batch_ws(self, reqs):
         return 100 * len(reqs)
@@ -179,10 +179,10 @@ class FakeBackend:
             n = self.pool.entries[r.entry].n
             r.out = np.arange(n, dtype=np.int32)
             r.stats = {"n": n}
-        self.keep[id(stream)] = max(self.held(stream), 50 * len(reqs))
+        self.kept = max(self.kept, 150 * len(reqs))
 
     def release(self):
-        self.keep.clear()
+        self.kept = 0
 
 
 def test_server_threads_drain_a_mixed_stream():
@@ -196,7 +196,7 @@ def test_server_threads_drain_a_mixed_stream():
     assert summ["solves"] == 200 and all(r.out is not None and r.error is None for r in reqs)
     assert all(r.out.size == pool.entries[r.entry].n for r in reqs)
     assert any(b and c > 1 for c, b in be.calls)  # requests were batched
-    assert summ["retained_bytes"] == sum(be.keep.values())
+    assert summ["retained_bytes"] == be.kept
     assert summ["peak_accounted_bytes"] <= summ["budget_bytes"]
 
 
