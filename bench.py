@@ -221,7 +221,7 @@ def bench_served(args):
     sweep = []
     checked = 0
     for j, rate in enumerate(rates):
-        count = args.requests or int(min(600, max(60, 3 * rate)))
+        count = args.requests or int(min(600, max(120, 3 * rate)))
         reqs, summ = serve.run_served(pool, weights, rate=rate, count=count, seed=11 + j,
                                       budget_bytes=args.budget_gib << 30)
         base_reqs, base = serve.run_one_at_a_time(pool, weights, rate=rate, count=count,
@@ -372,7 +372,7 @@ def main():
     ap.add_argument("--rates", default="10,20,40,80,160,320,640,1280",
                     help="served: arrival rates per second")
     ap.add_argument("--requests", type=int, default=0,
-                    help="served: requests per rate (0: 3 s of arrivals, 60 to 600)")
+                    help="served: requests per rate (0: 3 s of arrivals, 120 to 600)")
     ap.add_argument("--large-sizes", type=lambda s: [int(x) for x in s.split(",")],
                     default=[200_000, 500_000, 1_000_000], help="served: large request sizes")
     ap.add_argument("--budget-gib", type=int, default=64, help="served: HBM admission budget")

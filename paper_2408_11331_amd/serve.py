@@ -290,7 +290,10 @@ class Server:
         self.large_n = int(large_n)
         self.max_batch = int(max_batch)
         self.queue = collections.deque()
-        self.cv = threading.Condition()
+        self.lock = threading.Lock()
+        # workers wait on their kind's condition: an arrival wakes one worker
+        # of its kind; a finished call (memory, idle state) wakes them all
+        self.kind_cv = {False: threading.Condition(self.lock), True: threading.Condition(self.lock)}
         self.running = True
         self.completed: List[Request] = []
         self.retained = 0       # workspace the library keeps on the device (its figure)
@@ -310,6 +313,7 @@ class Server:
             self.threads.append(threading.Thread(target=self._worker, args=(w, large, warm, ready),
                                                  daemon=True))
         self.warm_errors: List[str] = []
+        self.warm_lock = threading.Lock()
         for t in self.threads:
             t.start()
         ready.wait()
@@ -326,15 +330,19 @@ class Server:
     def submit(self, entry: int, rid: int = 0) -> Request:
         req = Request(entry, rid=rid)
         req.arrival = time.perf_counter()
-        with self.cv:
+        with self.lock:
             self.queue.append(req)
-            self.cv.notify_all()
+            self.kind_cv[self.pool.entries[entry].n > self.large_n].notify()
         return req
 
+    def _wake_all(self):  # caller holds the lock
+        for c in self.kind_cv.values():
+            c.notify_all()
+
     def close(self):
-        with self.cv:
+        with self.lock:
             self.running = False
-            self.cv.notify_all()
+            self._wake_all()
         for t in self.threads:
             t.join()
 
@@ -349,11 +357,14 @@ class Server:
         if not mine:
             return
         e = max(mine, key=lambda x: x.n) if large else min(mine, key=lambda x: x.n)
-        self.backend.solve([Request(e.index)], stream)
-        if not large and e.t_batch is not None:
-            self.backend.solve([Request(e.index) for _ in range(3)], stream, batched=True)
-        with self.cv:
-            self.retained = self.backend.held()
+        # one warm-up at a time: the later ones reuse the workspace the first
+        # left, so warming up takes no more memory than one request does
+        with self.warm_lock:
+            self.backend.solve([Request(e.index)], stream)
+            if not large and e.t_batch is not None:
+                self.backend.solve([Request(e.index) for _ in range(3)], stream, batched=True)
+            with self.lock:
+                self.retained = self.backend.held()
 
     def _worker(self, w: int, large: bool, warm: bool, ready):
         stream = self.backend.make_stream()
@@ -363,14 +374,15 @@ class Server:
             if warm:
                 self._warm(w, large, stream)
         except Exception as e:
-            with self.cv:
+            with self.lock:
                 self.warm_errors.append(f"worker {w}: {type(e).__name__}: {e}")
             ready.wait()
             return
         ready.wait()
         inf = float("inf")
+        cv = self.kind_cv[large]
         while True:
-            with self.cv:
+            with self.lock:
                 while True:
                     # a request another worker holds back for memory goes first:
                     # take nothing that arrived after it
@@ -383,7 +395,9 @@ class Server:
                         idle=idle, before=before,
                         workers=self.kinds.count(large))
                     if picked:
-                        self.blocked[w] = None
+                        if self.blocked[w] is not None:  # others may take later requests now
+                            self.blocked[w] = None
+                            self._wake_all()
                         if reclaim:
                             self.backend.release()
                             self.retained = 0
@@ -395,7 +409,7 @@ class Server:
                         return
                     self.blocked[w] = head.arrival if head is not None and \
                         head.arrival < before else None
-                    self.cv.wait()
+                    cv.wait()
                 for r in picked:
                     self.queue.remove(r)
                 self.growth[w] = growth
@@ -413,7 +427,7 @@ class Server:
                 for r in picked:
                     r.error = f"{type(e).__name__}: {e}"
             t1 = time.perf_counter()
-            with self.cv:
+            with self.lock:
                 self.growth[w] = 0
                 if held is not None:
                     self.retained = held
@@ -421,7 +435,7 @@ class Server:
                     r.done_at = t1
                     self.completed.append(r)
                     r.event.set()
-                self.cv.notify_all()
+                self._wake_all()
 
 
 def latency_summary(reqs: List[Request]) -> dict:
