@@ -311,19 +311,19 @@ def golden_record(inst, init_kind, digest):
 
 
 def scorer_source_sha():
-    """sha256 of the scoring kernels' source: the shared header and pass.hip
-    through the end of k_score_tile (the control and apply kernels follow)."""
+    """sha256 of the pass kernels' source (the shared header and pass.hip):
+    the scoring kernels of a pass (status, tiled, list and wave-per-vertex
+    scorers) and the kernels around them."""
     csrc = os.path.join(ROOT, "paper_2408_11331_amd", "csrc")
     hdr = open(os.path.join(csrc, "impl.h"), "rb").read()
     src = open(os.path.join(csrc, "pass.hip"), "rb").read()
-    i = src.index(b"void k_score_tile(")
-    j = src.index(b"\n}\n", i) + 3
-    return hashlib.sha256(hdr + src[:j]).hexdigest()
+    return hashlib.sha256(hdr + src).hexdigest()
 
 
 def traffic_from_profile(kernel_src_sha):
-    """HBM bytes per scoring launch measured by rocprofv3 counters, if the
-    committed measurement was taken on the current kernel source."""
+    """HBM bytes per pass of the scoring kernels measured by rocprofv3
+    counters, if the committed measurement was taken on the current kernel
+    source."""
     p = os.path.join(ROOT, "profiles", "score_gmm_knn_traffic.json")
     if not os.path.exists(p):
         return None
