@@ -320,11 +320,12 @@ def scorer_source_sha():
     return hashlib.sha256(hdr + src).hexdigest()
 
 
-def traffic_from_profile(kernel_src_sha):
+def traffic_from_profile(kernel_src_sha, init="p0"):
     """HBM bytes per pass of the scoring kernels measured by rocprofv3
     counters, if the committed measurement was taken on the current kernel
     source."""
-    p = os.path.join(ROOT, "profiles", "score_gmm_knn_traffic.json")
+    name = "score_gmm_knn_traffic.json" if init == "p0" else "score_gmm_knn_singleton_traffic.json"
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     try:
@@ -460,8 +461,9 @@ def main():
     per_launch = pass_bytes(inst)
     achieved = per_launch / (launch_ms / 1000.0) / 1e9
     per_launch_b = boundary_bytes(inst, passes, st_ref["boundary"], accepted) / passes
-    # the counters were taken on this workload from the first input partition
-    traffic = traffic_from_profile(scorer_source_sha()) if args.init == "p0" else None
+    # counters taken on this workload (2 M kNN graph), for the start in use
+    traffic = traffic_from_profile(scorer_source_sha(), args.init) \
+        if args.workload == "gmm_knn" and not args.n else None
     # the solve against the oracle's stored result for this very instance
     gold = golden_record(inst, args.init, digest)
     if gold is not None:
