@@ -81,6 +81,16 @@ extern "C" {
                                    tables fit (they are chosen automatically
                                    when dense tables would not fit or would be
                                    far larger; results do not depend on it) */
+#define MCC_F_HASH_ROWS 0x80u /* hashed tables: use the row layout (keys
+                                 (cluster, label id) with the label ids of
+                                 every partition aligned to partition 0's,
+                                 each key owning a row of k counts) whenever
+                                 its indices fit, not only where it is no
+                                 larger than the key layout; results do not
+                                 depend on it */
+#define MCC_F_HASH_KEYS 0x100u /* hashed tables: always use the key layout
+                                  (one slot per (cluster, partition, label));
+                                  results do not depend on it */
 
 /* CSR graph: row_ptr[n + 1] (int64, row_ptr[0] = 0, non-decreasing,
  * row_ptr[n] = nnz) and col[nnz] (int32 vertex ids in [0, n)).  Arcs are
@@ -127,7 +137,8 @@ typedef struct {
                               scoring kernels of the executed passes */
   int32_t lanes_used;      /* the `lanes` the scoring ran with (0 = tiled) */
   int32_t tables;          /* contingency table layout used: 0 dense blocked,
-                              1 dense interleaved, 2 hashed */
+                              1 dense interleaved, 2 hashed keys, 3 hashed
+                              rows */
   int64_t skipped_evals;   /* of candidate_evals, those not recomputed because
                               an exact bound showed the vertex could not
                               propose (with MCC_F_SYMMETRIC; they count in

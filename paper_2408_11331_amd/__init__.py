@@ -18,6 +18,7 @@ MCC_ESCRATCH = -6
 NOALLOC_SCRATCH_BYTES = 256 << 20
 MCC_F_VALIDATE, MCC_F_TRACE, MCC_F_LITERAL, MCC_F_PROFILE = 0x1, 0x2, 0x4, 0x8
 MCC_F_ARC_CACHE, MCC_F_HASH_TABLES, MCC_F_SYMMETRIC = 0x10, 0x20, 0x40
+MCC_F_HASH_ROWS, MCC_F_HASH_KEYS = 0x80, 0x100
 
 # every function include/mcc.h declares
 EXPORTS = ("mcc_consensus", "mcc_consensus_noalloc", "mcc_objective", "mcc_mirkin", "mcc_canonicalize",

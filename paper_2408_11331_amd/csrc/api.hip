@@ -332,6 +332,7 @@ struct Solve {
   int32_t maxL = 0;        // largest label id bound of the final tables
   int64_t total = 0;       // table cells
   int64_t* acc = nullptr;  // sum s^2, sum |P_il|^2, sum N^2
+  uint8_t* rdist = nullptr;  // hashed rows: distinct label ids per vertex
 };
 
 // Largest cluster count for which labels are aligned to clusters.
@@ -413,12 +414,67 @@ void compact_labels_finish(Arena& ar, int64_t n, int32_t k, const std::vector<in
   launch_label_ids(out->scan, out->loff, k, out->max_span, out->fmap, st);
 }
 
+// Hashed layouts: the reference-aligned alignment is run when partition 0
+// has at most kAlignMaxClusters labels and its blocked table against the
+// other partitions stays within kRowsAlignCells counts.
+constexpr int64_t kRowsAlignCells = (int64_t)1 << 27;
+
+// Choices a caller may force (results do not depend on them).
+constexpr uint32_t kHashForce = 1;  // hashed tables even where dense ones fit
+constexpr uint32_t kHashRows = 2;   // hashed rows whenever their indices fit
+constexpr uint32_t kHashKeys = 4;   // hashed keys, no alignment
+
+// Label ids of every partition aligned to partition 0's: the alignment of
+// the interleaved layout, with partition 0's labels in the place of the
+// clusters (its table is counted on a sample of the vertices; any injective
+// relabelling is exact).  Partition 0 keeps its ids.  Rewrites fmap; *L2
+// (device) and L2h get the new id bounds.
+void align_to_reference(Arena& ar, Solve* S, int32_t maxL, int64_t sumL, int32_t** L2,
+                        std::vector<int32_t>* L2h, hipStream_t st) {
+  const int32_t k = S->k;
+  const int64_t n = S->n;
+  const std::vector<int32_t>& Lh = S->lab.Lh;
+  const int32_t L0 = Lh[0];
+  int32_t* Cref = ar.get<int32_t>(n);
+  launch_ref_labels(S->lab.dlabels, S->lab.loff, S->lab.fmap, n, Cref, st);
+  std::vector<int64_t> toff(k + 1, 0), poff(k + 1, 0);
+  for (int i = 0; i < k; ++i) {
+    toff[i + 1] = toff[i] + (int64_t)L0 * Lh[i];
+    poff[i + 1] = poff[i] + Lh[i];
+  }
+  int64_t* dtoff = ar.get<int64_t>(k + 1);
+  h2d(dtoff, ar.host(toff), k + 1, st);
+  int64_t* dpoff = ar.get<int64_t>(k + 1);
+  h2d(dpoff, ar.host(poff), k + 1, st);
+  Tables bt{};
+  bt.N = ar.get<int32_t>(toff[k]);
+  launch_fill_i32(bt.N, toff[k], 0, st);
+  bt.toff = dtoff;
+  bt.L = S->lab.L;
+  bt.k = k;
+  const int64_t stride = std::max<int64_t>(1, n / (1 << 18));
+  launch_build(Cref, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, L0, maxL, bt, st, stride);
+  uint64_t* win = ar.get<uint64_t>((int64_t)k * L0);
+  int32_t* home = ar.get<int32_t>(sumL);
+  uint64_t* key = ar.get<uint64_t>(sumL);
+  int32_t* extra = ar.get<int32_t>(sumL + 1);
+  int32_t* rank = ar.get<int32_t>(sumL + 1);
+  int32_t* tmp = ar.get<int32_t>(scan_tmp_elems(sumL));
+  int32_t* amap = ar.get<int32_t>(sumL);
+  *L2 = ar.get<int32_t>(k);
+  launch_align(bt, k, L0, maxL, dpoff, sumL, win, home, key, extra, rank, tmp, amap, *L2, st);
+  launch_fmap_update(S->lab.scan, S->lab.loff, dpoff, amap, k, S->lab.max_span, S->lab.fmap, st);
+  L2h->assign(k, 0);
+  d2h(L2h->data(), *L2, k, st);
+  sync(st);
+}
+
 // The full setup: compaction of labels and clusters, tables, initial
 // objective.  `init` null means singletons.  `want_rows` builds the
-// vertex-major label rows the passes read.
+// vertex-major label rows the passes read.  hash_mode: kHash* bits.
 void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
                  const int32_t* init, bool want_rows, const mcc_csr* g_validate, Solve* S,
-                 hipStream_t st, bool force_hash = false) {
+                 hipStream_t st, uint32_t hash_mode = 0) {
   const int32_t k = (int32_t)hptrs.size();
   S->n = n;
   S->k = k;
@@ -475,41 +531,90 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
   // than the n k keys a hashed table holds at most (unless they can be
   // aligned: dense_cells_max).
   const int64_t dense = (int64_t)K0 * sumL;
-  if (force_hash || dense > dense_cells_max(n, k, K0, sumL, want_rows)) {
+  if ((hash_mode & kHashForce) || dense > dense_cells_max(n, k, K0, sumL, want_rows)) {
     int bits = 12;
     while (((int64_t)1 << bits) < 4 * n * (int64_t)k) ++bits;
     const int64_t slots = (int64_t)1 << bits;
     if (slots > kMaxHashSlots) throw Status{MCC_ENOTSUP};
-    std::vector<int64_t> poff(k + 1, 0);
-    for (int i = 0; i < k; ++i) poff[i + 1] = poff[i] + Lh[i];
-    int64_t* dpoff = ar.get<int64_t>(k + 1);
-    h2d(dpoff, ar.host(poff), k + 1, st);
     Tables t{};
-    t.N = ar.get<int32_t>(4 * slots);
-    t.toff = dpoff;
-    t.L = S->lab.L;
     t.k = k;
     t.hashed = 1;
-    t.hshift = 64 - bits;
-    t.hmask = (uint64_t)slots - 1;
     int32_t* hc = ar.get<int32_t>(2);
     launch_fill_i32(hc, 2, 0, st);
     t.hocc = hc;
     t.herr = hc + 1;
+    // Hashed rows when the aligned labels give few rows: every live row
+    // (x, l) holds a label id l of one of x's members, so no clustering has
+    // more live rows than the singletons' T0 (the sum over vertices of
+    // their distinct ids), and a pass adds at most T0 more, so more than
+    // 2 T0 rows always leave an empty one (rebuilds keep the table about
+    // half full in practice).  Taken when that table is no larger than the
+    // key table and its cell indices fit 31 bits.
+    std::vector<int32_t> Lk = Lh;  // label id bounds of the table's keys
+    const int32_t* Lk_dev = S->lab.L;
+    bool rows = false;
+    if (want_rows && !(hash_mode & kHashKeys) && Lh[0] <= kAlignMaxClusters &&
+        (int64_t)Lh[0] * sumL <= kRowsAlignCells) {
+      int32_t* L2 = nullptr;
+      std::vector<int32_t> L2h;
+      align_to_reference(ar, S, maxL, sumL, &L2, &L2h, st);
+      Lk = L2h;
+      Lk_dev = L2;
+      S->Lvm = ar.get<int32_t>(n * k);
+      launch_label_transpose(S->lab.dlabels, k, n, S->lab.loff, S->lab.fmap, S->Lvm, st);
+      uint8_t* rdist = ar.get<uint8_t>(n);
+      int64_t* tot = ar.get<int64_t>(1);
+      launch_fill_u64(reinterpret_cast<uint64_t*>(tot), 1, 0ull, st);
+      launch_row_distinct(S->Lvm, n, k, rdist, tot, st);
+      int64_t T0 = 0;
+      d2h(&T0, tot, 1, st);
+      sync(st);
+      int rbits = 12;
+      while (((int64_t)1 << rbits) <= 2 * T0) ++rbits;
+      const int64_t R = (int64_t)1 << rbits;
+      const bool fits = R * k + 2 * (int64_t)K0 < ((int64_t)1 << 31);
+      const bool smaller = R * (8 + 4 * (int64_t)k) <= 16 * slots;
+      if (fits && (smaller || (hash_mode & kHashRows))) {
+        rows = true;
+        t.rows = 1;
+        t.rkeys = ar.get<uint64_t>(R);
+        t.N = ar.get<int32_t>(R * k);
+        launch_fill_i32(t.N, R * k, 0, st);
+        t.hshift = 64 - rbits;
+        t.hmask = (uint64_t)R - 1;
+        S->rdist = rdist;
+        S->total = R * k;
+      }
+    }
+    int32_t maxLk = 1;
+    std::vector<int64_t> poff(k + 1, 0);
+    for (int i = 0; i < k; ++i) {
+      poff[i + 1] = poff[i] + Lk[i];
+      maxLk = std::max(maxLk, Lk[i]);
+    }
+    int64_t* dpoff = ar.get<int64_t>(k + 1);
+    h2d(dpoff, ar.host(poff), k + 1, st);
+    t.toff = dpoff;
+    t.L = Lk_dev;
+    if (!rows) {
+      t.N = ar.get<int32_t>(4 * slots);
+      t.hshift = 64 - bits;
+      t.hmask = (uint64_t)slots - 1;
+      S->total = slots;
+    }
     launch_hash_clear(t, st);
-    launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, maxL, t, st);
+    launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, maxLk, t, st);
     S->t = t;
-    S->maxL = maxL;
-    S->total = slots;
-    if (want_rows) {
+    S->maxL = maxLk;
+    if (want_rows && !S->Lvm) {
       S->Lvm = ar.get<int32_t>(n * k);
       launch_label_transpose(S->lab.dlabels, k, n, S->lab.loff, S->lab.fmap, S->Lvm, st);
     }
     S->acc = ar.get<int64_t>(3);
     launch_fill_u64(reinterpret_cast<uint64_t*>(S->acc), 3, 0ull, st);
-    int32_t* hist = ar.get<int32_t>(sumL);
-    launch_objective0_hashed(t, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, S->s, sumL,
-                             hist, K0 == n, S->acc, st);
+    int32_t* hist = ar.get<int32_t>(poff[k]);
+    launch_objective0_hashed(t, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, S->s,
+                             poff[k], hist, K0 == n, S->acc, st);
     return;
   }
   // Blocked tables with dense label ids: the final tables when the labels
@@ -695,7 +800,9 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
     std::vector<const int32_t*> hptrs(labels, labels + k);
     Solve S;
     build_solve(ar, hptrs, n, init, true, (flags & MCC_F_VALIDATE) ? g : nullptr, &S, st,
-                (flags & MCC_F_HASH_TABLES) != 0);
+                ((flags & MCC_F_HASH_TABLES) ? kHashForce : 0u) |
+                    ((flags & MCC_F_HASH_ROWS) ? kHashRows : 0u) |
+                    ((flags & MCC_F_HASH_KEYS) ? kHashKeys : 0u));
 
     int64_t* dtrace = nullptr;
     if (flags & MCC_F_TRACE) dtrace = ar.get<int64_t>((int64_t)max_rounds * 4);
@@ -766,6 +873,7 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
       if (hs) throw Status{MCC_EGRAPH};
     }
     a.hflag = S.t.hashed ? ar.get<int32_t>(1) : nullptr;
+    a.rdist = S.t.rows ? S.rdist : nullptr;
     a.K0 = S.K0;
     if (S.t.hashed) {
       a.mstart = ar.get<int32_t>((int64_t)S.K0 + 1);
@@ -877,7 +985,7 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
       stats->ms_passes = ms;
       stats->boundary = hc.boundary;
       stats->lanes_used = lanes;
-      stats->tables = S.t.hashed ? 2 : (S.t.interleaved ? 1 : 0);
+      stats->tables = S.t.hashed ? (S.t.rows ? 3 : 2) : (S.t.interleaved ? 1 : 0);
       if (profile) {
         float tot = 0.f;
         for (int j = 0; j < hc.passes && 2 * j + 1 < (int)pev.size(); ++j) {
@@ -1881,6 +1989,21 @@ int mcc_workspace_bound(int64_t n, int64_t nnz, int32_t k, int64_t max_label, in
     while (((int64_t)1 << bits) < 4 * nk) ++bits;
     add(8 * (k + 1)); add(16 * ((int64_t)1 << bits)); add(8); add(4 * sumL);
     add(4 * (K0 + 1)); add(4 * K0); add(4 * n); add(4 * (scan_tmp_elems(K0) + 1));
+    // alignment to partition 0 for the row layout (its table is at most the
+    // key table unless forced) and its label ids (at most L0 + L_i a partition)
+    const int64_t L0 = std::min<int64_t>(max_label + 1, kAlignMaxClusters);
+    if (L0 * sumL <= kRowsAlignCells) {
+      add(4 * n); add(8 * (k + 1)); add(8 * (k + 1)); add(4 * L0 * sumL); add(8 * k * L0);
+      add(4 * sumL); add(8 * sumL); add(4 * (sumL + 1)); add(4 * (sumL + 1));
+      add(4 * (scan_tmp_elems(sumL) + 1)); add(4 * sumL); add(4 * k); add(n); add(8);
+      add(8 * (k + 1)); add(4 * (sumL + k * L0));
+      if (flags & MCC_F_HASH_ROWS) {
+        int rbits = 12;
+        while (((int64_t)1 << rbits) <= 2 * nk && ((int64_t)2 << rbits) * k < ((int64_t)1 << 31))
+          ++rbits;
+        add(8 * ((int64_t)1 << rbits)); add(4 * k * ((int64_t)1 << rbits));
+      }
+    }
     std::swap(small, hsmall);
     std::swap(big, hbig);
   }

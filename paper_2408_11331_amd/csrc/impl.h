@@ -37,6 +37,7 @@ struct Ctl {
   int32_t defer_all;        // 1: this pass's vertices all go to the wave-per-vertex
                             // scorer (most had too many candidates for the tiles)
   int64_t skipped;          // candidate evaluations proven unnecessary (all passes)
+  int64_t prop_rows;        // hashed rows: rows the current pass's proposals can add
   int64_t* trace;           // device int64[max_rounds * 4] or null
 };
 
@@ -57,7 +58,13 @@ constexpr int32_t kErrGraph = 4;
 //    toff[i] the first global label id of partition i, for cluster counts
 //    whose dense tables would not fit (e.g. singleton starts).  Keys are
 //    never removed; a slot whose count drops to 0 stays, and the table is
-//    rebuilt from the partition before it could fill beyond half.
+//    rebuilt from the partition before it could fill beyond half;
+//  - hashed rows: the same open addressing over keys x << 32 | l alone
+//    (rkeys, 8 bytes a row), each key owning a row of k counts N[r * k + i]
+//    (partition i, label id l in that partition).  With the label ids of
+//    every partition aligned to one reference partition, most partitions
+//    give a vertex the same id, so the k counts a vertex reads for one
+//    cluster mostly share one key and one row.
 // A "cell" is the index of one counter: the dense position, or the slot.
 struct Tables {
   int32_t* N;           // dense: the counts; hashed: the slots as int32 words
@@ -72,6 +79,9 @@ struct Tables {
   uint64_t hmask;       // hashed: slots - 1
   int32_t* hocc;        // hashed: occupied slots
   int32_t* herr;        // hashed: set if an insert found no slot
+  uint64_t* rkeys;      // hashed rows: the row keys (N holds the rows' counts)
+  int32_t rows;         // 1: hashed rows
+  int32_t pad2;
 };
 
 constexpr uint64_t kHashEmpty = ~0ull;
@@ -85,7 +95,8 @@ __device__ inline uint32_t cell(const Tables& t, int i, int32_t x, int32_t l) {
 }
 
 __device__ inline uint64_t hkey(const Tables& t, int i, int32_t x, int32_t l) {
-  return ((uint64_t)(uint32_t)x << 32) | (uint64_t)(t.toff[i] + l);
+  return t.rows ? (((uint64_t)(uint32_t)x << 32) | (uint64_t)(uint32_t)l)
+                : (((uint64_t)(uint32_t)x << 32) | (uint64_t)(t.toff[i] + l));
 }
 
 __device__ inline uint64_t hstart(const Tables& t, uint64_t key) {
@@ -132,16 +143,61 @@ __device__ inline uint32_t hslot(const Tables& t, uint64_t key, int32_t& claimed
   return 0;
 }
 
-// The counter of a cell.
+// Hashed rows: the row of `key`, -1 if absent (reads only).
+__device__ inline int64_t rfind(const Tables& t, uint64_t key) {
+  uint64_t h = hstart(t, key);
+  for (uint64_t q = 0; q <= t.hmask; ++q) {
+    const uint64_t kk = t.rkeys[h];
+    if (kk == key) return (int64_t)h;
+    if (kk == kHashEmpty) return -1;
+    h = (h + 1) & t.hmask;
+  }
+  return -1;
+}
+
+// Hashed rows: the row of `key`, claimed if absent (as hslot).
+__device__ inline uint32_t rslot(const Tables& t, uint64_t key, int32_t& claimed) {
+  unsigned long long* K = reinterpret_cast<unsigned long long*>(t.rkeys);
+  uint64_t h = hstart(t, key);
+  for (uint64_t q = 0; q <= t.hmask; ++q) {
+    const uint64_t kk = K[h];
+    if (kk == key) return (uint32_t)h;
+    if (kk == kHashEmpty) {
+      const uint64_t prev = atomicCAS(&K[h], (unsigned long long)kHashEmpty,
+                                      (unsigned long long)key);
+      if (prev == kHashEmpty) {
+        ++claimed;
+        return (uint32_t)h;
+      }
+      if (prev == key) return (uint32_t)h;
+    }
+    h = (h + 1) & t.hmask;
+  }
+  atomicOr(t.herr, 1);
+  return 0;
+}
+
+// The counter of a cell (hashed rows: cells are row * k + i).
 __device__ inline int32_t* counter(const Tables& t, uint32_t c) {
-  return t.hashed ? t.N + 4 * (uint64_t)c + 2 : t.N + c;
+  return (t.hashed && !t.rows) ? t.N + 4 * (uint64_t)c + 2 : t.N + c;
 }
 
 // Cell of (i, x, l) for an update: the dense position, or the key's slot
-// (claimed if new).
+// (claimed if new), or its row's counter of partition i.
 __device__ inline uint32_t cell_upd(const Tables& t, int i, int32_t x, int32_t l,
                                     int32_t& claimed) {
-  return t.hashed ? hslot(t, hkey(t, i, x, l), claimed) : cell(t, i, x, l);
+  if (!t.hashed) return cell(t, i, x, l);
+  if (t.rows) return rslot(t, hkey(t, i, x, l), claimed) * (uint32_t)t.k + (uint32_t)i;
+  return hslot(t, hkey(t, i, x, l), claimed);
+}
+
+// Hashed tables: the count of (i, x, l), 0 if absent.
+__device__ inline int32_t hcount(const Tables& t, int i, int32_t x, int32_t l) {
+  if (t.rows) {
+    const int64_t r = rfind(t, hkey(t, i, x, l));
+    return r < 0 ? 0 : t.N[(uint64_t)r * (uint64_t)t.k + (uint64_t)i];
+  }
+  return hget(t, hkey(t, i, x, l));
 }
 
 // Add the wave's claimed slots to the occupancy counter (all lanes of the
@@ -154,7 +210,7 @@ __device__ inline void flush_claims(const Tables& t, int32_t claimed) {
 
 // Count of (i, x, l) for scoring.
 __device__ inline int32_t count_of(const Tables& t, int i, int32_t x, int32_t l) {
-  return t.hashed ? hget(t, hkey(t, i, x, l)) : t.N[cell(t, i, x, l)];
+  return t.hashed ? hcount(t, i, x, l) : t.N[cell(t, i, x, l)];
 }
 
 // ---- setup kernels (setup.hip) -------------------------------------------
@@ -225,6 +281,13 @@ void launch_objective0_hashed(const Tables& t, const int32_t* const* dlabels, co
                               const int32_t* fmap, int64_t n, int32_t k, int32_t K0,
                               const int32_t* s, int64_t total_labels, int32_t* hist,
                               bool singletons, int64_t* acc, hipStream_t st);
+// Hashed rows: the reference labels (partition 0's label ids) the other
+// partitions are aligned to, and each vertex's distinct label ids (the
+// rows it contributes to; *total, zeroed by the caller, gets their sum).
+void launch_ref_labels(const int32_t* const* dlabels, const int64_t* loff, const int32_t* fmap,
+                       int64_t n, int32_t* Cref, hipStream_t st);
+void launch_row_distinct(const int32_t* Lvm, int64_t n, int32_t k, uint8_t* rdist, int64_t* total,
+                         hipStream_t st);
 // In-arc lists: in_ptr (exclusive scan of in-degrees, n + 1) and in_pos
 // (arc positions grouped by head vertex); ac[j] = C[col[j]].
 void launch_in_degree(const int32_t* col, int64_t nnz, int32_t* indeg, hipStream_t st);
@@ -292,6 +355,8 @@ struct PassArgs {
   const int32_t* in_pos;
   int64_t cells;      // table cells (keys >= cells address cluster sizes)
   int32_t* hflag;     // hashed tables: 1 while the current pass rebuilds them
+  const uint8_t* rdist;  // hashed rows: distinct label ids of each vertex (the rows
+                         // its move can add), else null
   // Hashed tables: member lists of the clusters as they stand at the start of
   // the pass (members[mstart[x] .. mstart[x + 1]) are the vertices of x), so
   // that a small cluster's agreement sum is taken over its members' label
@@ -386,7 +451,7 @@ template <int TK>
 __device__ inline int32_t count_t(const Tables& t, int i, int32_t x, int32_t l) {
   if (TK == kInterleaved)
     return t.N[((uint32_t)x * (uint32_t)t.Lmax + (uint32_t)l) * (uint32_t)t.k + i];
-  if (TK == kHashed) return hget(t, hkey(t, i, x, l));
+  if (TK == kHashed) return hcount(t, i, x, l);
   return t.N[(uint32_t)t.toff[i] + (uint32_t)x * (uint32_t)t.L[i] + (uint32_t)l];
 }
 

@@ -216,7 +216,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         }
       } else if (a.t.hashed) {
         const uint64_t ky = (uint64_t)(uint32_t)y << 32;
-        if (kfits) {  // implies lds_geom
+        if (kfits && a.t.rows) {
+#pragma unroll
+          for (int t = 0; t < KR; ++t) {
+            int i = lane + t * G;
+            if (i < k) sum += hcount(a.t, i, y, lab[t]);
+          }
+        } else if (kfits) {  // implies lds_geom
 #pragma unroll
           for (int t = 0; t < KR; ++t) {
             int i = lane + t * G;
@@ -1289,6 +1295,7 @@ __global__ __launch_bounds__(kBlock) void k_props(PassArgs a) {
   constexpr int V = 4;
   constexpr int64_t kChunk = (int64_t)V * kBlock;
   const int t = threadIdx.x;
+  int64_t rows = 0;  // hashed rows: the rows the proposals can add
   for (int64_t c0 = (int64_t)blockIdx.x * kChunk; c0 < a.n; c0 += (int64_t)gridDim.x * kChunk) {
     bool pr[V];
     int32_t mine = 0;
@@ -1297,6 +1304,7 @@ __global__ __launch_bounds__(kBlock) void k_props(PassArgs a) {
       const int64_t v = c0 + j * kBlock + t;
       pr[j] = v < a.n && a.prop[v] >= 0;
       mine += pr[j];
+      if (pr[j] && a.rdist) rows += a.rdist[v];
     }
     int32_t total;
     int32_t off = block_exclusive_scan(mine, &total);
@@ -1309,6 +1317,17 @@ __global__ __launch_bounds__(kBlock) void k_props(PassArgs a) {
         if (pr[j]) a.plist[off++] = (int32_t)(c0 + j * kBlock + t);
     }
     __syncthreads();
+  }
+  if (a.rdist) {  // one atomic per workgroup
+    __shared__ int64_t s_rows[kBlock / 64];
+    rows = wave_sum64(rows);
+    if ((t & 63) == 0) s_rows[t >> 6] = rows;
+    __syncthreads();
+    if (t == 0) {
+      int64_t tot = 0;
+      for (int j = 0; j < kBlock / 64; ++j) tot += s_rows[j];
+      if (tot) atomicAdd((unsigned long long*)&ctl->prop_rows, (unsigned long long)tot);
+    }
   }
 }
 
@@ -1615,22 +1634,38 @@ __global__ __launch_bounds__(kBlock) void k_apply(PassArgs a) {
 
 // Hashed tables: before the batch is applied, rebuild the table from the
 // partition (the counts are a function of C alone) if the keys the batch may
-// add could take it beyond half full.  The batch adds at most k keys per
-// proposal; the table holds 4 n k slots or more and at most n k live keys, so
-// after a rebuild there is always room.
+// add could take it beyond half full.  Keys: the batch adds at most k keys
+// per proposal; the table holds 4 n k slots or more and at most n k live
+// keys, so after a rebuild there is always room.  Rows: a proposal adds at
+// most its vertex's distinct label ids, at most T0 in all, over at most T0
+// live rows, in more than 2 T0 rows.  The first pass's table is the one
+// just built (no key without a count), so a rebuild would not change it.
 __global__ void k_hash_guard(PassArgs a, int64_t limit) {
   Ctl* ctl = a.ctl;
   if (ctl->done) {
     *a.hflag = 0;
     return;
   }
-  const bool need = (int64_t)*a.t.hocc + (int64_t)a.k * ctl->nprop > limit;
+  // keys the batch may add: k a proposal, or for hashed rows the distinct
+  // label ids of the proposers (the rows a move can add)
+  const int64_t adds = a.t.rows ? ctl->prop_rows : (int64_t)a.k * ctl->nprop;
+  const bool need = ctl->passes > 1 && (int64_t)*a.t.hocc + adds > limit;
   *a.hflag = need ? 1 : 0;
   if (need) *a.t.hocc = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_hash_reset(PassArgs a) {
   if (!*a.hflag) return;
+  if (a.t.rows) {  // empty keys, zero counts
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j <= (int64_t)a.t.hmask;
+         j += (int64_t)gridDim.x * kBlock)
+      a.t.rkeys[j] = kHashEmpty;
+    const int64_t cells = ((int64_t)a.t.hmask + 1) * a.k;
+    for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < cells;
+         j += (int64_t)gridDim.x * kBlock)
+      a.t.N[j] = 0;
+    return;
+  }
   uint4* H = reinterpret_cast<uint4*>(a.t.N);
   const uint4 empty = make_uint4(0xffffffffu, 0xffffffffu, 0u, 0u);
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j <= (int64_t)a.t.hmask;
@@ -1646,7 +1681,7 @@ __global__ __launch_bounds__(kBlock) void k_hash_refill(PassArgs a) {
        j += (int64_t)gridDim.x * kBlock) {
     const int64_t v = j / a.k;
     const int i = (int)(j - v * a.k);
-    atomicAdd(counter(a.t, hslot(a.t, hkey(a.t, i, a.C[v], a.Lvm[j]), claimed)), 1);
+    atomicAdd(counter(a.t, cell_upd(a.t, i, a.C[v], a.Lvm[j], claimed)), 1);
   }
   flush_claims(a.t, claimed);
 }
@@ -1696,6 +1731,7 @@ __global__ void k_end(Ctl* ctl) {
   ctl->heavy_count = 0;
   ctl->rescore_count = 0;
   ctl->plist_count = 0;
+  ctl->prop_rows = 0;
   ctl->dS2 = 0;
   ctl->dN2 = 0;
   if (ctl->passes >= ctl->max_rounds) ctl->done = 1;
@@ -1765,12 +1801,12 @@ void enqueue_pass(const PassArgs& a, int lanes, int grid_score, int grid_apply, 
   }
   if (score_end) (void)hipEventRecord(score_end, st);
   k_begin<<<1, 1, 0, st>>>(a.ctl, a.pc);
+  k_props<<<grid_apply, kBlock, 0, st>>>(a);
   if (a.t.hashed) {
     k_hash_guard<<<1, 1, 0, st>>>(a, (int64_t)((a.t.hmask + 1) / 2));
     k_hash_reset<<<grid_apply, kBlock, 0, st>>>(a);
     k_hash_refill<<<grid_apply, kBlock, 0, st>>>(a);
   }
-  k_props<<<grid_apply, kBlock, 0, st>>>(a);
   if (a.delta_lds > 0) {
     const dim3 grid((unsigned)a.delta_slices, (unsigned)a.k);
     if (a.t.interleaved) k_apply_delta<true><<<grid, kBlock, a.delta_lds, st>>>(a);

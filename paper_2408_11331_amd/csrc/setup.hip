@@ -447,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_sumsq(const int32_t* __restri
   for (uint32_t j = (uint32_t)gtid(); j < total; j += (uint32_t)gstride()) {
     const uint32_t v = j / (uint32_t)k;
     const int i = (int)(j - v * (uint32_t)k);
-    s += t.hashed ? hget(t, hkey(t, i, C[v], Lvm[j])) : t.N[cell(t, i, C[v], Lvm[j])];
+    s += count_of(t, i, C[v], Lvm[j]);
   }
   s = block_sum<int64_t>(s);
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)acc, (unsigned long long)s);
@@ -455,9 +455,46 @@ __global__ __launch_bounds__(kBlock) void k_gather_sumsq(const int32_t* __restri
 
 // ---- hashed tables ---------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_hash_clear(Tables t) {
+  if (t.rows) {  // the keys (the caller zeroes the counts)
+    for (int64_t j = gtid(); j <= (int64_t)t.hmask; j += gstride()) t.rkeys[j] = kHashEmpty;
+    return;
+  }
   uint4* H = reinterpret_cast<uint4*>(t.N);
   const uint4 empty = make_uint4(0xffffffffu, 0xffffffffu, 0u, 0u);
   for (int64_t j = gtid(); j <= (int64_t)t.hmask; j += gstride()) H[j] = empty;
+}
+
+// Cref[v] = label id of v in partition 0 (the reference of the row alignment)
+__global__ __launch_bounds__(kBlock) void k_ref_labels(const int32_t* const* __restrict__ labels,
+                                                       const int64_t* __restrict__ loff,
+                                                       const int32_t* __restrict__ fmap, int64_t n,
+                                                       int32_t* __restrict__ Cref) {
+  const int32_t* p = labels[0];
+  const int32_t* map = fmap + loff[0];
+  for (int64_t v = gtid(); v < n; v += gstride()) Cref[v] = map[p[v]];
+}
+
+// rdist[v] = distinct label ids in v's row (the rows of a hashed-rows table
+// v contributes to); *total += their sum
+__global__ __launch_bounds__(kBlock) void k_row_distinct(const int32_t* __restrict__ Lvm,
+                                                         int64_t n, int32_t k,
+                                                         uint8_t* __restrict__ rdist,
+                                                         int64_t* __restrict__ total) {
+  int64_t s = 0;
+  for (int64_t v = gtid(); v < n; v += gstride()) {
+    const int32_t* r = Lvm + v * k;
+    int32_t d = 0;
+    for (int i = 0; i < k; ++i) {
+      const int32_t l = r[i];
+      bool seen = false;
+      for (int j = 0; j < i && !seen; ++j) seen = r[j] == l;
+      d += !seen;
+    }
+    rdist[v] = (uint8_t)min(d, 255);
+    s += d;
+  }
+  s = block_sum<int64_t>(s);
+  if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)total, (unsigned long long)s);
 }
 
 // hist[toff[i] + l] = |P_i l| (label ids in the hashed key space)
@@ -855,10 +892,13 @@ void launch_objective0_hashed(const Tables& t, const int32_t* const* dlabels, co
   dim3 g(grid_for(n, kBlock * 16, 64), k);
   k_label_hist<<<g, kBlock, 0, st>>>(dlabels, loff, fmap, t.toff, n, hist);
   k_sumsq<<<grid_for(total_labels, kBlock, 2048), kBlock, 0, st>>>(hist, total_labels, acc + 1);
+  const int64_t slots = (int64_t)t.hmask + 1;
   if (singletons)
     launch_fill_u64(reinterpret_cast<uint64_t*>(acc + 2), 1, (uint64_t)(n * (int64_t)k), st);
+  else if (t.rows)
+    k_sumsq<<<grid_for(slots * k, kBlock, 4096), kBlock, 0, st>>>(t.N, slots * k, acc + 2);
   else
-    k_slot_sumsq<<<grid_for((int64_t)t.hmask + 1, kBlock * 4, 4096), kBlock, 0, st>>>(t, acc + 2);
+    k_slot_sumsq<<<grid_for(slots, kBlock * 4, 4096), kBlock, 0, st>>>(t, acc + 2);
 }
 
 void launch_check_symmetric(const int64_t* row_ptr, const int32_t* col, int64_t n,
@@ -924,6 +964,16 @@ void launch_canonical_write(const int32_t* in, int64_t n, const int32_t* first,
 void launch_dense_map(const int32_t* in, int64_t n, const int32_t* scan, int32_t* out,
                       hipStream_t st) {
   k_dense_map<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(in, n, scan, out);
+}
+
+void launch_ref_labels(const int32_t* const* dlabels, const int64_t* loff, const int32_t* fmap,
+                       int64_t n, int32_t* Cref, hipStream_t st) {
+  if (n > 0) k_ref_labels<<<grid_for(n, kBlock, 2048), kBlock, 0, st>>>(dlabels, loff, fmap, n, Cref);
+}
+
+void launch_row_distinct(const int32_t* Lvm, int64_t n, int32_t k, uint8_t* rdist, int64_t* total,
+                         hipStream_t st) {
+  if (n > 0) k_row_distinct<<<grid_for(n, kBlock, 4096), kBlock, 0, st>>>(Lvm, n, k, rdist, total);
 }
 
 }  // namespace mcc

@@ -113,11 +113,14 @@ def test_random_instances(mcc, seed, n, k, init):
     assert_same(run_gpu(mcc, inst, ini, flags=mcc.MCC_F_ARC_CACHE), o)
     # candidate sets carried over between passes (the graphs are symmetric)
     assert_same(run_gpu(mcc, inst, ini, flags=mcc.MCC_F_SYMMETRIC | mcc.MCC_F_VALIDATE), o)
-    # counts in the open-addressing table instead of dense tables
+    # counts in the open-addressing tables instead of dense tables: one slot
+    # per (cluster, partition, label), or rows of k counts keyed by
+    # (cluster, aligned label)
     for lanes in (0, [64, 32, 16, 8, 4][seed % 5]):
-        g = run_gpu(mcc, inst, ini, lanes=lanes, flags=mcc.MCC_F_HASH_TABLES)
-        assert g[1]["tables"] == 2
-        assert_same(g, o)
+        for layout, code in ((mcc.MCC_F_HASH_KEYS, 2), (mcc.MCC_F_HASH_ROWS, 3)):
+            g = run_gpu(mcc, inst, ini, lanes=lanes, flags=mcc.MCC_F_HASH_TABLES | layout)
+            assert g[1]["tables"] == code
+            assert_same(g, o)
 
 
 @pytest.mark.parametrize("n,k", [(301, 600), (1000, 3), (517, 50), (5, 9)])
@@ -129,7 +132,8 @@ def test_label_row_shapes(mcc, n, k):
     announce(f"label rows n={n} k={k}")
     inst = synth.random_instance(n, k, avg_deg=6.0, n_labels=13, seed=n + k, init="random")
     o = run_oracle(inst)
-    for flags in (0, mcc.MCC_F_HASH_TABLES):
+    for flags in (0, mcc.MCC_F_HASH_TABLES | mcc.MCC_F_HASH_KEYS,
+                  mcc.MCC_F_HASH_TABLES | mcc.MCC_F_HASH_ROWS):
         assert_same(run_gpu(mcc, inst, flags=flags), o)
 
 
@@ -231,14 +235,19 @@ def test_fallback_swap_instance(mcc):
 def test_singleton_start_hashed_auto(mcc):
     # the paper's singleton start on an LFR-style graph: dense tables would
     # hold n * sum_i L_i = 17.6 M cells for 160 k keys, so the library picks
-    # the hashed table by itself; exact parity with the oracle
+    # a hashed layout by itself; exact parity with the oracle in both
+    # hashed layouts
     announce("singleton lfr n=20000 k=8 (hashed)")
     inst = synth.lfr(n=20000, k=8)
     o = run_oracle(inst, None)
     assert o[1]["fallback_rounds"] >= 1
-    for kw in ({}, {"flags": mcc.MCC_F_ARC_CACHE}, {"lanes": 16}):
+    keys, rows = mcc.MCC_F_HASH_KEYS, mcc.MCC_F_HASH_ROWS
+    for kw, code in (({}, (2, 3)), ({"flags": mcc.MCC_F_ARC_CACHE}, (2, 3)),
+                     ({"lanes": 16}, (2, 3)), ({"flags": keys}, (2,)),
+                     ({"flags": rows}, (3,)), ({"flags": rows, "lanes": 64}, (3,)),
+                     ({"flags": rows | mcc.MCC_F_SYMMETRIC}, (3,))):
         g = run_gpu(mcc, inst, None, **kw)
-        assert g[1]["tables"] == 2
+        assert g[1]["tables"] in code, (kw, g[1]["tables"])
         assert_same(g, o)
 
 
@@ -251,7 +260,7 @@ def test_singleton_start_large_properties(mcc):
     announce("singleton lfr n=400000 k=16 (hashed, properties)")
     inst = synth.lfr(n=400_000, k=16)
     out, st, tr = run_gpu(mcc, inst, None)
-    assert st["tables"] == 2 and st["converged"] == 1
+    assert st["tables"] in (2, 3) and st["converged"] == 1
     obj = [st["objective_init"]] + [int(r[3]) for r in tr]
     for r, before, after in zip(tr, obj[:-1], obj[1:]):
         assert (after < before) if r[1] > 0 else (after == before)
