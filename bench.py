@@ -490,7 +490,7 @@ def main():
         "config": {
             "workload": args.workload, "n": inst.n, "nnz": inst.nnz, "k": inst.k,
             "init": "input partition 0" if args.init == "p0" else "singletons",
-            "tables": ["dense blocked", "dense interleaved", "hashed"][st_ref["tables"]],
+            "tables": ["dense blocked", "dense interleaved", "hashed keys", "hashed rows"][st_ref["tables"]],
             "symmetric_flag": bool(args.symmetric),
             "passes": passes, "moves": st_ref["moves"],
             "candidate_evals_per_solve": st_ref["candidate_evals"],

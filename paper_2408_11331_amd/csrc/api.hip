@@ -418,6 +418,9 @@ void compact_labels_finish(Arena& ar, int64_t n, int32_t k, const std::vector<in
 // has at most kAlignMaxClusters labels and its blocked table against the
 // other partitions stays within kRowsAlignCells counts.
 constexpr int64_t kRowsAlignCells = (int64_t)1 << 27;
+// Hashed rows: clusters up to this size are scored from member rows (a
+// row-table probe costs about as many lines as two member rows).
+constexpr int32_t kRowsMemberMax = 2;
 
 // Choices a caller may force (results do not depend on them).
 constexpr uint32_t kHashForce = 1;  // hashed tables even where dense ones fit
@@ -603,7 +606,10 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
       S->total = slots;
     }
     launch_hash_clear(t, st);
-    launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, maxLk, t, st);
+    if (rows)  // from the vertex-major rows: a vertex's k updates share few rows
+      launch_build_rows(S->C, S->Lvm, n, k, t, st);
+    else
+      launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, maxLk, t, st);
     S->t = t;
     S->maxL = maxLk;
     if (want_rows && !S->Lvm) {
@@ -880,6 +886,7 @@ int consensus_impl(const mcc_csr* g, const int32_t* const* labels, int32_t k,
       a.mcnt = ar.get<int32_t>(S.K0);
       a.members = ar.get<int32_t>(n);
       a.mscan_tmp = ar.get<int32_t>(scan_tmp_elems(S.K0));
+      a.msum_max = S.t.rows ? kRowsMemberMax : kMemberSumMax;
     }
     a.cn_bytes = S.K0 <= 256 ? 1 : (S.K0 <= 65536 ? 2 : 4);
     if (a.cn_bytes == 4) {

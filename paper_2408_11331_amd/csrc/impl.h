@@ -288,6 +288,9 @@ void launch_ref_labels(const int32_t* const* dlabels, const int64_t* loff, const
                        int64_t n, int32_t* Cref, hipStream_t st);
 void launch_row_distinct(const int32_t* Lvm, int64_t n, int32_t k, uint8_t* rdist, int64_t* total,
                          hipStream_t st);
+// Hashed rows: the counts of C from the vertex-major label rows.
+void launch_build_rows(const int32_t* C, const int32_t* Lvm, int64_t n, int32_t k, Tables t,
+                       hipStream_t st);
 // In-arc lists: in_ptr (exclusive scan of in-degrees, n + 1) and in_pos
 // (arc positions grouped by head vertex); ac[j] = C[col[j]].
 void launch_in_degree(const int32_t* col, int64_t nnz, int32_t* indeg, hipStream_t st);
@@ -365,6 +368,10 @@ struct PassArgs {
   int32_t* mcnt;      // K0 (fill cursors)
   int32_t* members;   // n
   int32_t* mscan_tmp;
+  int32_t msum_max;   // largest cluster scored from member rows (at most
+                      // kMemberSumMax): a member row costs two or three
+                      // lines, a key table's probes k lines, a row table's
+                      // a few
   int32_t K0;
   // Narrow copy of C (uint8 when K0 <= 256, uint16 when K0 <= 65536, else
   // C itself) for the per-arc cluster gathers: a few MiB stay resident in

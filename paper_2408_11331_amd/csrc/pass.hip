@@ -142,7 +142,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
       s_ilarge[kW][kI];
   __shared__ __align__(8) int32_t s_vrow[kW][(LIST && G == 64) ? 64 : 2];
   __shared__ int32_t s_cset[kW][(LIST && G == 64) ? kCandSet : 1];
+  __shared__ int32_t s_cnb[kW][(LIST && G == 64) ? kCandSet : 1];  // a neighbour in the cluster
   __shared__ int32_t s_clist[kW][(LIST && G == 64) ? 128 : 1];
+  __shared__ int32_t s_cnbl[kW][(LIST && G == 64) ? 128 : 1];
   __shared__ int32_t s_ccount[kW];
   const int lane = threadIdx.x & (G - 1);
   const int64_t group = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
@@ -194,7 +196,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
     // S_y(v) summed over the group's lanes
     auto agree = [&](int32_t y) -> int32_t {
       int32_t sum = 0;
-      if (a.members && a.s[y] <= kMemberSumMax) {
+      if (a.members && a.s[y] <= a.msum_max) {
         // S_y(v) = sum over members u of y of the partitions agreeing on u, v;
         // the member ids are read once, one per lane, and broadcast
         const int32_t cnt = a.s[y], b = a.mstart[y];
@@ -267,6 +269,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
         // the smallest (gain, cluster id) taken by a wave reduction
         const int w = threadIdx.x >> 6;
         int32_t* cset = s_cset[w];
+        int32_t* cnb = s_cnb[w];
         for (int j = lane; j < kCandSet; j += 64) cset[j] = -1;
         if (lane == 0) s_ccount[w] = 0;
         __builtin_amdgcn_wave_barrier();
@@ -280,6 +283,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             if (cur == -1) {
               cur = atomicCAS(&cset[h], -1, y);
               if (cur == -1) {
+                // the arc's head: a candidate of one vertex has it as its
+                // only member
+                cnb[h] = a.col[beg + r * 64 + lane];
                 atomicAdd(&s_ccount[w], 1);
                 break;
               }
@@ -302,9 +308,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
           int32_t total;
           int32_t pos = wave_excl_scan(mine, &total);
           int32_t* clist = s_clist[w];
+          int32_t* cnbl = s_cnbl[w];
 #pragma unroll
           for (int q = 0; q < kCandSet / 64; ++q)
-            if (keys[q] != -1) clist[pos++] = keys[q];
+            if (keys[q] != -1) {
+              cnbl[pos] = cnb[lane + 64 * q];
+              clist[pos++] = keys[q];
+            }
           __builtin_amdgcn_wave_barrier();
           cand_lo = lane < nc ? clist[lane] : kInf;
           cand_hi = 64 + lane < nc ? clist[64 + lane] : kInf;
@@ -343,11 +353,21 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
             const int32_t yB = lane == 0 ? lo_prev : hi_prev;
             const int32_t yC = hi_prev;
             const bool vA = lane < nitems, vB = 64 + lane < nitems, vC = lane == 0 && 128 < nitems;
+            // a member of each item: v for its own cluster, else the head of
+            // an arc into the candidate (candidate c is item c + 1)
+            const int32_t* cnbl = s_cnbl[w];
+            const int32_t uA = lane == 0 ? (int32_t)v : (vA ? cnbl[lane - 1] : -1);
+            const int32_t uB = vB ? cnbl[63 + lane] : -1;
+            const int32_t uC = vC ? cnbl[127] : -1;
             const int32_t zA = vA ? a.s[yA] : 0, zB = vB ? a.s[yB] : 0, zC = vC ? a.s[yC] : 0;
-            const bool smA = vA && zA <= kMemberSumMax, smB = vB && zB <= kMemberSumMax,
-                       smC = vC && zC <= kMemberSumMax;
-            const int32_t mA = smA ? a.mstart[yA] : 0, mB = smB ? a.mstart[yB] : 0,
-                          mC = smC ? a.mstart[yC] : 0;
+            const bool smA = vA && zA <= a.msum_max, smB = vB && zB <= a.msum_max,
+                       smC = vC && zC <= a.msum_max;
+            // member list start, or ~u for a cluster whose one member u is known
+            auto mlist = [&](bool sm, int32_t z, int32_t u, int32_t y) -> int32_t {
+              return !sm ? 0 : ((z == 1 && u >= 0) ? ~u : a.mstart[y]);
+            };
+            const int32_t mA = mlist(smA, zA, uA, yA), mB = mlist(smB, zB, uB, yB),
+                          mC = mlist(smC, zC, uC, yC);
             int32_t totA, totB, lgA, lgB;
             const int32_t exA = wave_excl_scan(smA ? zA : 0, &totA);
             const int32_t exB = wave_excl_scan(smB ? zB : 0, &totB);
@@ -403,7 +423,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                   if (p < P) {
                     const int it = item_of(p);
                     its[e] = it;
-                    const int32_t u = a.members[imst[it] + (p - ioff[it])];
+                    const int32_t ms = imst[it];
+                    const int32_t u = ms < 0 ? ~ms : a.members[ms + (p - ioff[it])];
                     const int2* ru = reinterpret_cast<const int2*>(a.Lvm + (int64_t)u * k);
 #pragma unroll
                     for (int t = 0; t < 8; ++t)
@@ -426,7 +447,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) 
                 int32_t sum = 0, it = -1;
                 if (p < P) {
                   it = item_of(p);
-                  const int32_t u = a.members[imst[it] + (p - ioff[it])];
+                  const int32_t ms = imst[it];
+                  const int32_t u = ms < 0 ? ~ms : a.members[ms + (p - ioff[it])];
                   const int32_t* ru = a.Lvm + (int64_t)u * k;
 #pragma unroll
                   for (int t = 0; t < 16; ++t)
@@ -844,7 +866,7 @@ void k_score_tile(PassArgs a) {
 #pragma unroll
         for (int q = 0; q < kProbeBatch; ++q) {
           int32_t sum = 0;
-          if (TK == kHashed && xs[q] >= 0 && a.members && a.s[xs[q]] <= kMemberSumMax) {
+          if (TK == kHashed && xs[q] >= 0 && a.members && a.s[xs[q]] <= a.msum_max) {
             const int32_t cnt = a.s[xs[q]];  // <= kProbeLanes: one member id per lane
             const int32_t mid = lane < cnt ? a.members[a.mstart[xs[q]] + lane] : 0;
             for (int32_t m = 0; m < cnt; ++m) {
@@ -887,7 +909,7 @@ void k_score_tile(PassArgs a) {
           int32_t sum = 0;
           if (x >= 0) {
             const int32_t* row = a.Lvm + ro;
-            if (TK == kHashed && a.members && a.s[x] <= kMemberSumMax) {
+            if (TK == kHashed && a.members && a.s[x] <= a.msum_max) {
               const int32_t cnt = a.s[x];
               const int32_t mid = lane < cnt ? a.members[a.mstart[x] + lane] : 0;
               for (int32_t m = 0; m < cnt; ++m) {
@@ -1693,7 +1715,7 @@ __global__ __launch_bounds__(kBlock) void k_member_fill(PassArgs a) {
   for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < a.n;
        v += (int64_t)gridDim.x * kBlock) {
     const int32_t x = a.C[v];
-    if (a.s[x] <= kMemberSumMax)  // larger clusters are probed, not listed
+    if (a.s[x] <= a.msum_max)  // larger clusters are probed, not listed
       a.members[a.mstart[x] + atomicAdd(&a.mcnt[x], 1)] = (int32_t)v;
   }
 }

@@ -475,26 +475,61 @@ __global__ __launch_bounds__(kBlock) void k_ref_labels(const int32_t* const* __r
 }
 
 // rdist[v] = distinct label ids in v's row (the rows of a hashed-rows table
-// v contributes to); *total += their sum
+// v contributes to); *total += their sum.  k <= 64: a wave per vertex, lane
+// i holding partition i, the first lane of each id counted by a ballot;
+// else a thread per vertex.
 __global__ __launch_bounds__(kBlock) void k_row_distinct(const int32_t* __restrict__ Lvm,
                                                          int64_t n, int32_t k,
                                                          uint8_t* __restrict__ rdist,
                                                          int64_t* __restrict__ total) {
   int64_t s = 0;
-  for (int64_t v = gtid(); v < n; v += gstride()) {
-    const int32_t* r = Lvm + v * k;
-    int32_t d = 0;
-    for (int i = 0; i < k; ++i) {
-      const int32_t l = r[i];
-      bool seen = false;
-      for (int j = 0; j < i && !seen; ++j) seen = r[j] == l;
-      d += !seen;
+  if (k <= 64) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * kBlock) >> 6;
+    for (int64_t v = gtid() >> 6; v < n; v += nw) {
+      const int32_t l = lane < k ? Lvm[v * k + lane] : -1;
+      bool first = lane < k;
+      for (int j = 0; j < k; ++j) {
+        const int32_t o = __shfl(l, j, 64);
+        if (j < lane && o == l) first = false;
+      }
+      const int32_t d = (int32_t)__popcll(__ballot(first));
+      if (lane == 0) {
+        rdist[v] = (uint8_t)min(d, 255);
+        s += d;
+      }
     }
-    rdist[v] = (uint8_t)min(d, 255);
-    s += d;
+  } else {
+    for (int64_t v = gtid(); v < n; v += gstride()) {
+      const int32_t* r = Lvm + v * k;
+      int32_t d = 0;
+      for (int i = 0; i < k; ++i) {
+        const int32_t l = r[i];
+        bool seen = false;
+        for (int j = 0; j < i && !seen; ++j) seen = r[j] == l;
+        d += !seen;
+      }
+      rdist[v] = (uint8_t)min(d, 255);
+      s += d;
+    }
   }
   s = block_sum<int64_t>(s);
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)total, (unsigned long long)s);
+}
+
+// Hashed rows: N[row(C[v], Lvm[v k + i]) k + i] += 1 for every (v, i),
+// vertex-major (a vertex's partitions mostly share one row)
+__global__ __launch_bounds__(kBlock) void k_build_rows(const int32_t* __restrict__ C,
+                                                       const int32_t* __restrict__ Lvm, int64_t n,
+                                                       int32_t k, Tables t) {
+  int32_t claimed = 0;
+  const int64_t total = n * k;
+  for (int64_t j = gtid(); j < total; j += gstride()) {
+    const int64_t v = j / k;
+    const int i = (int)(j - v * k);
+    atomicAdd(counter(t, cell_upd(t, i, C[v], Lvm[j], claimed)), 1);
+  }
+  flush_claims(t, claimed);
 }
 
 // hist[toff[i] + l] = |P_i l| (label ids in the hashed key space)
@@ -974,6 +1009,11 @@ void launch_ref_labels(const int32_t* const* dlabels, const int64_t* loff, const
 void launch_row_distinct(const int32_t* Lvm, int64_t n, int32_t k, uint8_t* rdist, int64_t* total,
                          hipStream_t st) {
   if (n > 0) k_row_distinct<<<grid_for(n, kBlock, 4096), kBlock, 0, st>>>(Lvm, n, k, rdist, total);
+}
+
+void launch_build_rows(const int32_t* C, const int32_t* Lvm, int64_t n, int32_t k, Tables t,
+                       hipStream_t st) {
+  if (n > 0) k_build_rows<<<grid_for(n * k, kBlock, 8192), kBlock, 0, st>>>(C, Lvm, n, k, t);
 }
 
 }  // namespace mcc
