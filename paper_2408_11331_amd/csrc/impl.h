@@ -200,6 +200,42 @@ __device__ inline int32_t hcount(const Tables& t, int i, int32_t x, int32_t l) {
   return hget(t, hkey(t, i, x, l));
 }
 
+// Hashed rows: N[row(C[v], Lvm[j]) k + i] += 1 for every j = v k + i in
+// [0, n k), the grid's threads (tid of stride) taking four items at a time
+// with their first probes in flight together (a key found there needs no
+// probe loop).  The wave's claims are added to the occupancy counter.
+__device__ inline int32_t rows_count(const Tables& t, const int32_t* __restrict__ C,
+                                     const int32_t* __restrict__ Lvm, int64_t n, int32_t k,
+                                     int64_t tid, int64_t stride) {
+  constexpr int U = 4;
+  int32_t claimed = 0;
+  const int64_t total = n * k;
+  for (int64_t j0 = tid; j0 < total; j0 += U * stride) {
+    uint64_t key[U], h[U], kk[U];
+    int32_t ii[U];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + u * stride;
+      ok[u] = j < total;
+      const int64_t jc = ok[u] ? j : 0;
+      const int64_t v = jc / k;
+      ii[u] = (int32_t)(jc - v * k);
+      key[u] = hkey(t, 0, C[v], Lvm[jc]);
+      h[u] = hstart(t, key[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) kk[u] = t.rkeys[h[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!ok[u]) continue;
+      const uint64_t r = kk[u] == key[u] ? h[u] : (uint64_t)rslot(t, key[u], claimed);
+      atomicAdd(t.N + r * (uint64_t)t.k + (uint64_t)ii[u], 1);
+    }
+  }
+  return claimed;
+}
+
 // Add the wave's claimed slots to the occupancy counter (all lanes of the
 // wave call it).
 __device__ inline void flush_claims(const Tables& t, int32_t claimed) {

@@ -1697,6 +1697,12 @@ __global__ __launch_bounds__(kBlock) void k_hash_reset(PassArgs a) {
 
 __global__ __launch_bounds__(kBlock) void k_hash_refill(PassArgs a) {
   if (!*a.hflag) return;
+  if (a.t.rows) {
+    flush_claims(a.t, rows_count(a.t, a.C, a.Lvm, a.n, a.k,
+                                 (int64_t)blockIdx.x * kBlock + threadIdx.x,
+                                 (int64_t)gridDim.x * kBlock));
+    return;
+  }
   const int64_t total = a.n * a.k;
   int32_t claimed = 0;
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < total;

@@ -522,14 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_row_distinct(const int32_t* __restri
 __global__ __launch_bounds__(kBlock) void k_build_rows(const int32_t* __restrict__ C,
                                                        const int32_t* __restrict__ Lvm, int64_t n,
                                                        int32_t k, Tables t) {
-  int32_t claimed = 0;
-  const int64_t total = n * k;
-  for (int64_t j = gtid(); j < total; j += gstride()) {
-    const int64_t v = j / k;
-    const int i = (int)(j - v * k);
-    atomicAdd(counter(t, cell_upd(t, i, C[v], Lvm[j], claimed)), 1);
-  }
-  flush_claims(t, claimed);
+  flush_claims(t, rows_count(t, C, Lvm, n, k, gtid(), gstride()));
 }
 
 // hist[toff[i] + l] = |P_i l| (label ids in the hashed key space)
