@@ -19,6 +19,9 @@ namespace mcc {
 // setup.hip
 void launch_dense_map(const int32_t* in, int64_t n, const int32_t* scan, int32_t* out,
                       hipStream_t st);
+// Hashed rows from clusters of one vertex each: the counts stored, not added.
+void launch_build_rows_single(const int32_t* C, const int32_t* Lvm, int64_t n, int32_t k,
+                              Tables t, hipStream_t st);
 }
 
 namespace {
@@ -606,7 +609,9 @@ void build_solve(Arena& ar, const std::vector<const int32_t*>& hptrs, int64_t n,
       S->total = slots;
     }
     launch_hash_clear(t, st);
-    if (rows)  // from the vertex-major rows: a vertex's k updates share few rows
+    if (rows && K0 == n)  // one vertex a cluster: every row has one owner
+      launch_build_rows_single(S->C, S->Lvm, n, k, t, st);
+    else if (rows)  // from the vertex-major rows: a vertex's k updates share few rows
       launch_build_rows(S->C, S->Lvm, n, k, t, st);
     else
       launch_build(S->C, S->lab.dlabels, S->lab.loff, S->lab.fmap, n, k, K0, maxLk, t, st);

@@ -517,6 +517,24 @@ __global__ __launch_bounds__(kBlock) void k_row_distinct(const int32_t* __restri
   if (threadIdx.x == 0 && s) atomicAdd((unsigned long long*)total, (unsigned long long)s);
 }
 
+// Hashed rows from clusters of one vertex each (singletons): row (C[v], l)
+// belongs to v alone, so its counts are stored, 1 at the partitions where
+// v has label id l (the others stay at the zero they were filled with);
+// each cell is written by one thread
+__global__ __launch_bounds__(kBlock) void k_build_rows_single(const int32_t* __restrict__ C,
+                                                              const int32_t* __restrict__ Lvm,
+                                                              int64_t n, int32_t k, Tables t) {
+  int32_t claimed = 0;
+  const int64_t total = n * k;
+  for (int64_t j = gtid(); j < total; j += gstride()) {
+    const int64_t v = j / k;
+    const int i = (int)(j - v * k);
+    const uint32_t r = rslot(t, hkey(t, 0, C[v], Lvm[j]), claimed);
+    t.N[(uint64_t)r * (uint64_t)k + (uint64_t)i] = 1;
+  }
+  flush_claims(t, claimed);
+}
+
 // Hashed rows: N[row(C[v], Lvm[v k + i]) k + i] += 1 for every (v, i),
 // vertex-major (a vertex's partitions mostly share one row)
 __global__ __launch_bounds__(kBlock) void k_build_rows(const int32_t* __restrict__ C,
@@ -1002,6 +1020,12 @@ void launch_ref_labels(const int32_t* const* dlabels, const int64_t* loff, const
 void launch_row_distinct(const int32_t* Lvm, int64_t n, int32_t k, uint8_t* rdist, int64_t* total,
                          hipStream_t st) {
   if (n > 0) k_row_distinct<<<grid_for(n, kBlock, 4096), kBlock, 0, st>>>(Lvm, n, k, rdist, total);
+}
+
+void launch_build_rows_single(const int32_t* C, const int32_t* Lvm, int64_t n, int32_t k,
+                              Tables t, hipStream_t st) {
+  if (n > 0)
+    k_build_rows_single<<<grid_for(n * k, kBlock, 8192), kBlock, 0, st>>>(C, Lvm, n, k, t);
 }
 
 void launch_build_rows(const int32_t* C, const int32_t* Lvm, int64_t n, int32_t k, Tables t,
