@@ -1977,7 +1977,8 @@ int mcc_workspace_bound(int64_t n, int64_t nnz, int32_t k, int64_t max_label, in
   // can be chosen, the hashed table when it can
   const int64_t dense_cap = dense_cells_max(n, k, K0, sumL, true);
   const int64_t dense_ub = K0 * sumL;  // clusters x labels, at most
-  const bool can_hash = dense_ub > std::min<int64_t>(kMaxTableEntries, dense_cap);
+  const bool can_hash = (flags & MCC_F_HASH_TABLES) ||
+                        dense_ub > std::min<int64_t>(kMaxTableEntries, dense_cap);
   const int64_t dense = std::min<int64_t>(dense_ub, std::min<int64_t>(kMaxTableEntries, dense_cap));
   int64_t dsmall = 0, dbig = 0, hsmall = 0, hbig = 0;
   {
