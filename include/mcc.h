@@ -338,7 +338,9 @@ int mcc_batch_tune(const mcc_problem* probs, int32_t count, const mcc_batch_opts
  * values all lie in [0, max_label], started from an init with `clusters`
  * distinct ids (0: unknown, or singletons), with these flags: every array
  * it sizes from those figures (the contingency tables at the largest size
- * the layouts that can be chosen may take), arrays below the 16 MiB chunk
+ * the layouts that can be chosen may take: a hashed row table counts as the
+ * key table it may not exceed unless MCC_F_HASH_ROWS is set, plus the
+ * alignment to partition 0's labels), arrays below the 16 MiB chunk
  * size counted twice for the chunk ends they may leave unused, plus one
  * chunk.  The exact figure of a finished call is stats->workspace_bytes.
  *
