@@ -433,8 +433,8 @@ constexpr uint32_t kHashKeys = 4;   // hashed keys, no alignment
 // Label ids of every partition aligned to partition 0's: the alignment of
 // the interleaved layout, with partition 0's labels in the place of the
 // clusters (its table is counted on a sample of the vertices; any injective
-// relabelling is exact).  Partition 0 keeps its ids.  Rewrites fmap; *L2
-// (device) and L2h get the new id bounds.
+// relabelling is exact).  Partition 0's labels that the sample holds keep
+// their ids.  Rewrites fmap; *L2 (device) and L2h get the new id bounds.
 void align_to_reference(Arena& ar, Solve* S, int32_t maxL, int64_t sumL, int32_t** L2,
                         std::vector<int32_t>* L2h, hipStream_t st) {
   const int32_t k = S->k;
