@@ -251,6 +251,19 @@ def test_singleton_start_hashed_auto(mcc):
         assert_same(g, o)
 
 
+def test_hashed_keys_after_alignment(mcc):
+    # independent random labels: every vertex holds nearly k distinct ids,
+    # so the row table would be larger than the key table and the library
+    # keeps keys, over the label ids the reference alignment assigned
+    announce("hashed keys over aligned ids n=2000 k=20")
+    inst = synth.random_instance(2000, 20, 8.0, 50, seed=91, init="random")
+    for ini in (None, inst.init):
+        o = run_oracle(inst, ini)
+        g = run_gpu(mcc, inst, ini, flags=mcc.MCC_F_HASH_TABLES)
+        assert g[1]["tables"] == 2
+        assert_same(g, o)
+
+
 def test_singleton_start_large_properties(mcc):
     # 400 000 vertices from singletons (dense tables would need 400 000 x
     # sum_i L_i cells, beyond the dense limit): the oracle's whole solve is
