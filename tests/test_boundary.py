@@ -136,3 +136,26 @@ def test_bench_traffic_keyed_to_scorer_source():
     assert b.traffic_from_profile("0" * 64) is None
     t = b.traffic_from_profile(sha)
     assert t is None or t > 0
+
+
+def test_workspace_bound_properties():
+    # host-only sizing: grows with the instance, counts the hashed table when
+    # hashing is forced, and the row table when it is forced
+    if not os.path.exists(mcc.LIB_PATH):
+        pytest.skip("libmcc.so not built")
+    wb = mcc.workspace_bound
+    base = wb(100_000, 2_000_000, 16, 200, 500, 0)
+    assert base > 0
+    assert wb(200_000, 4_000_000, 16, 200, 500, 0) >= base
+    assert wb(100_000, 2_000_000, 32, 200, 500, 0) >= base
+    forced = wb(100_000, 2_000_000, 16, 200, 500, mcc.MCC_F_HASH_TABLES)
+    assert forced >= base
+    # the key table alone is 16 bytes a slot, 4 n k slots or more
+    assert forced - base >= 16 * 4 * 100_000 * 16 // 2
+    rows = wb(100_000, 2_000_000, 16, 200, 500, mcc.MCC_F_HASH_TABLES | mcc.MCC_F_HASH_ROWS)
+    assert rows > forced
+    # singletons choose hashing by themselves
+    single = wb(100_000, 2_000_000, 16, 200, 0, 0)
+    assert single >= 16 * 4 * 100_000 * 16
+    with pytest.raises(Exception):
+        wb(-1, 0, 1, 0, 0, 0)
